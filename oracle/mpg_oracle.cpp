@@ -1,0 +1,1366 @@
+// FP64 CPU oracle for the batched manifold-walk path of "Manifold Path Guiding
+// for Importance Sampling Specular Chains" (Fan et al., ACM TOG 42(6), 2023).
+//
+// TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct reference
+// that the tests, the benchmark's CPU-baseline leg and the smoke check run
+// beside the HIP path.  It shares no code, header, table or constant generator
+// with the HIP library; the two meet only through the seeded synthetic inputs.
+// The product path must never call it.
+//
+// What it follows (paper sections; the constraint and Newton details the paper
+// inherits by citation are restated from the geometry itself):
+//   * sub-path / chain notation x_0 = x_D, x_1..x_n, x_{n+1} = x_L  -- Sec. 3, Table 1
+//   * manifold walk = Newton's method + reprojection                 -- Sec. 3 "Manifold walks"
+//   * admissible chains: every specular vertex satisfies the law of
+//     reflection / refraction (generalized half-vector parallel to the
+//     shading normal)                                               -- Sec. 3 "Specular manifolds"
+//   * sub-path throughput T = kappa * G * L_o                          -- Eq. (ThroughputEval)
+//   * seed deduction x_i = r(x_{i-1}, s_tau(...))                      -- Eq. (deduction), Sec. 5.3
+//   * initial distribution p_0 (x_1 uniform on specular surfaces)     -- Sec. 5.4
+//   * defensive one-sample MIS, alpha = 0.5                           -- Sec. 5.5 "Defensive sampling"
+//   * reciprocal probability by repeated trials, P(n) factored out    -- Sec. 5.8
+//   * sample weight w = T <1/P>                                       -- Eq. (eq_weight)
+// Every reading where the paper is silent is listed in the design notes
+// and restated at the function that implements it.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "dual.hpp"
+
+namespace oracle {
+
+static const double kInf = std::numeric_limits<double>::infinity();
+static const double kPi = 3.14159265358979323846;
+static const int KMAX = 8;
+
+enum Status : int8_t {
+  ST_CONVERGED = 0,
+  ST_MAX_ITER = 1,
+  ST_SINGULAR = 2,
+  ST_SIDE_INVALID = 3,
+  ST_OCCLUDED = 4,
+  ST_SEED_INVALID = 5,
+  ST_FP64_REJECT = 6,
+  ST_BAD_INPUT = 7,
+};
+enum Material : int { MAT_MIRROR = 0, MAT_DIELECTRIC = 1 };
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC 2011).  Round function:
+// two 64x64->128 multiplies, xor with the other counter words and the round
+// key; the key is bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+static inline void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+static void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]) {
+  uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint64_t k[2] = {key_in[0], key_in[1]};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k[0] += 0x9E3779B97F4A7C15ULL;
+      k[1] += 0xBB67AE8584CAA73BULL;
+    }
+    uint64_t h0, l0, h1, l1;
+    mulhilo64(0xD2E7470EE14C6C93ULL, c[0], &h0, &l0);
+    mulhilo64(0xCA5A826395121157ULL, c[2], &h1, &l1);
+    uint64_t n0 = h1 ^ c[1] ^ k[0], n2 = h0 ^ c[3] ^ k[1];
+    c[0] = n0; c[1] = l1; c[2] = n2; c[3] = l0;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+// Eight uniforms in [0, 1) with 24-bit resolution from one Philox block:
+// uniform j takes the high (j even) or low (j odd) 32-bit half of word j/2
+// and keeps its top 24 bits.
+struct Uniforms {
+  double u[8];
+};
+static Uniforms draw(uint64_t seed, uint64_t chain, uint64_t trial, uint64_t attempt) {
+  uint64_t ctr[4] = {chain, trial, attempt, 0};
+  uint64_t key[2] = {seed, 0};
+  uint64_t w[4];
+  philox4x64_10(ctr, key, w);
+  Uniforms U;
+  for (int j = 0; j < 8; ++j) {
+    uint64_t word = w[j >> 1];
+    uint32_t half = (j & 1) ? (uint32_t)(word & 0xffffffffULL) : (uint32_t)(word >> 32);
+    U.u[j] = (double)(half >> 8) * (1.0 / 16777216.0);
+  }
+  return U;
+}
+
+// splitmix64 finalizer (Steele, Lea, Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014) used to hash a chain's identity.
+static inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+static uint64_t solution_id(int n, int type, const int* prim) {
+  uint64_t h = splitmix64((uint64_t)n | ((uint64_t)type << 8));
+  for (int i = 0; i < n; ++i) h = splitmix64(h ^ (uint64_t)(uint32_t)prim[i]);
+  return h;
+}
+
+// Orthonormal basis around a unit vector: the branchless construction of
+// Duff, Burgess, Christensen, Hery, Kensler, Liani, Villemin, "Building an
+// orthonormal basis, revisited", JCGT 6(1), 2017.
+static void onb(const V3d& n, V3d* b1, V3d* b2) {
+  double sign = std::copysign(1.0, n.z);
+  double a = -1.0 / (sign + n.z);
+  double b = n.x * n.y * a;
+  *b1 = V3d(1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  *b2 = V3d(b, sign + n.y * n.y * a, -n.y);
+}
+
+// ---------------------------------------------------------------------------
+// Scene: triangles with vertex normals, analytic spheres, per-object material.
+// Primitive ids: triangles >= 0 (input order), spheres -1 - s.
+// ---------------------------------------------------------------------------
+struct HeightField {
+  int obj, res, first_vert, first_tri, n_sines;
+  double x0, x1, y0, y1, z0;
+  double amp[8], freq[8], psi[8], phase[8];
+};
+
+struct Node {
+  V3d lo, hi;
+  int left, right;   // children (interior) or -1
+  int start, count;  // leaf range in `order`
+};
+
+struct Scene {
+  std::vector<V3d> P, N;
+  std::vector<int> tri;  // 3 per triangle
+  std::vector<int> tri_obj;
+  std::vector<int> mat;
+  std::vector<double> ior;
+  std::vector<V3d> sc;
+  std::vector<double> sr;
+  std::vector<int> sobj;
+  double scale = 1.0;
+  std::vector<HeightField> hfs;
+  // median-split BVH over triangles
+  std::vector<Node> nodes;
+  std::vector<int> order;
+  // area-proportional primitive choice per object (index n_obj = all objects)
+  std::vector<std::vector<double>> cdf;
+  std::vector<std::vector<int>> cdf_prim;
+  // per object xy bounds (guided sampling domain)
+  std::vector<double> obj_lo_x, obj_lo_y, obj_hi_x, obj_hi_y;
+  double zmax = 0.0;
+  int ntri() const { return (int)tri_obj.size(); }
+  int nobj() const { return (int)mat.size(); }
+  int prim_obj(int prim) const { return prim >= 0 ? tri_obj[prim] : sobj[-1 - prim]; }
+};
+
+static void tri_verts(const Scene& s, int t, V3d* a, V3d* b, V3d* c) {
+  *a = s.P[s.tri[3 * t]];
+  *b = s.P[s.tri[3 * t + 1]];
+  *c = s.P[s.tri[3 * t + 2]];
+}
+
+static int build_node(Scene& s, std::vector<V3d>& cen, int start, int count) {
+  Node nd;
+  nd.lo = V3d(kInf, kInf, kInf);
+  nd.hi = V3d(-kInf, -kInf, -kInf);
+  V3d clo = nd.lo, chi = nd.hi;
+  for (int i = start; i < start + count; ++i) {
+    V3d v[3];
+    tri_verts(s, s.order[i], &v[0], &v[1], &v[2]);
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) {
+        nd.lo[a] = std::min(nd.lo[a], v[k][a]);
+        nd.hi[a] = std::max(nd.hi[a], v[k][a]);
+      }
+    for (int a = 0; a < 3; ++a) {
+      clo[a] = std::min(clo[a], cen[s.order[i]][a]);
+      chi[a] = std::max(chi[a], cen[s.order[i]][a]);
+    }
+  }
+  // pad the box so that rounding in the slab test cannot cull a true hit
+  for (int a = 0; a < 3; ++a) {
+    double pad = 1e-9 * (1.0 + std::fabs(nd.lo[a]) + std::fabs(nd.hi[a]));
+    nd.lo[a] -= pad;
+    nd.hi[a] += pad;
+  }
+  int idx = (int)s.nodes.size();
+  s.nodes.push_back(nd);
+  if (count <= 4) {
+    s.nodes[idx].left = s.nodes[idx].right = -1;
+    s.nodes[idx].start = start;
+    s.nodes[idx].count = count;
+    return idx;
+  }
+  int axis = 0;
+  double ext = chi.x - clo.x;
+  if (chi.y - clo.y > ext) { axis = 1; ext = chi.y - clo.y; }
+  if (chi.z - clo.z > ext) { axis = 2; }
+  int mid = start + count / 2;
+  std::nth_element(s.order.begin() + start, s.order.begin() + mid, s.order.begin() + start + count,
+                   [&](int a, int b) {
+                     if (cen[a][axis] != cen[b][axis]) return cen[a][axis] < cen[b][axis];
+                     return a < b;
+                   });
+  int l = build_node(s, cen, start, mid - start);
+  int r = build_node(s, cen, mid, start + count - mid);
+  s.nodes[idx].left = l;
+  s.nodes[idx].right = r;
+  s.nodes[idx].start = s.nodes[idx].count = 0;
+  return idx;
+}
+
+// Moller-Trumbore ray/triangle test in FP64 (edges inclusive).
+static bool hit_triangle(const V3d& o, const V3d& d, const V3d& a, const V3d& b, const V3d& c, double* t) {
+  V3d e1 = b - a, e2 = c - a;
+  V3d p = cross(d, e2);
+  double det = dot(e1, p);
+  if (det == 0.0) return false;
+  double inv = 1.0 / det;
+  V3d q = o - a;
+  double u = dot(q, p) * inv;
+  if (u < 0.0 || u > 1.0) return false;
+  V3d r = cross(q, e1);
+  double v = dot(d, r) * inv;
+  if (v < 0.0 || u + v > 1.0) return false;
+  *t = dot(e2, r) * inv;
+  return true;
+}
+
+struct Hit {
+  int prim = 0;
+  double t = kInf;
+  bool ok = false;
+};
+
+static void consider(Hit* h, int prim, double t) {
+  if (!h->ok || t < h->t || (t == h->t && prim < h->prim)) {
+    h->ok = true;
+    h->t = t;
+    h->prim = prim;
+  }
+}
+
+// Sphere hit.  A ray leaving a point of the same sphere (`own`) has the root
+// t = 0 at its origin; the other root t = -2 (o - c).d is the only candidate.
+static void sphere_hits(const Scene& s, const V3d& o, const V3d& d, int exclude, double tmin, Hit* h) {
+  for (size_t k = 0; k < s.sr.size(); ++k) {
+    int prim = -1 - (int)k;
+    V3d oc = o - s.sc[k];
+    double b = dot(oc, d);
+    if (prim == exclude) {
+      double t = -2.0 * b;
+      if (t > tmin) consider(h, prim, t);
+      continue;
+    }
+    double cc = dot(oc, oc) - s.sr[k] * s.sr[k];
+    double disc = b * b - cc;
+    if (disc < 0.0) continue;
+    double sq = std::sqrt(disc);
+    double t0 = -b - sq, t1 = -b + sq;
+    if (t0 > tmin) consider(h, prim, t0);
+    else if (t1 > tmin) consider(h, prim, t1);
+  }
+}
+
+// r(x, w): first intersection of the ray with the specular surfaces (Sec. 5.3),
+// skipping the primitive the ray starts on and anything closer than tmin.
+static Hit cast_ray(const Scene& s, const V3d& o, const V3d& d, int exclude, double tmin, bool brute = false) {
+  Hit h;
+  sphere_hits(s, o, d, exclude, tmin, &h);
+  if (s.ntri() == 0) return h;
+  if (brute) {
+    for (int t = 0; t < s.ntri(); ++t) {
+      if (t == exclude) continue;
+      V3d a, b, c;
+      tri_verts(s, t, &a, &b, &c);
+      double th;
+      if (hit_triangle(o, d, a, b, c, &th) && th > tmin) consider(&h, t, th);
+    }
+    return h;
+  }
+  V3d inv(1.0 / d.x, 1.0 / d.y, 1.0 / d.z);
+  std::vector<int> stack;
+  stack.reserve(64);
+  stack.push_back(0);
+  while (!stack.empty()) {
+    const Node& nd = s.nodes[stack.back()];
+    stack.pop_back();
+    double t0 = -kInf, t1 = kInf;
+    bool miss = false;
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] == 0.0) {
+        if (o[a] < nd.lo[a] || o[a] > nd.hi[a]) miss = true;
+        continue;
+      }
+      double ta = (nd.lo[a] - o[a]) * inv[a], tb = (nd.hi[a] - o[a]) * inv[a];
+      if (ta > tb) std::swap(ta, tb);
+      t0 = std::max(t0, ta);
+      t1 = std::min(t1, tb);
+    }
+    if (miss || t0 > t1 || t1 < tmin || (h.ok && t0 > h.t)) continue;
+    if (nd.left < 0) {
+      for (int i = nd.start; i < nd.start + nd.count; ++i) {
+        int t = s.order[i];
+        if (t == exclude) continue;
+        V3d a, b, c;
+        tri_verts(s, t, &a, &b, &c);
+        double th;
+        if (hit_triangle(o, d, a, b, c, &th) && th > tmin) consider(&h, t, th);
+      }
+    } else {
+      stack.push_back(nd.left);
+      stack.push_back(nd.right);
+    }
+  }
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// Local geometry of a specular vertex.  Each vertex has two degrees of
+// freedom y = (a, b) along an orthonormal tangent frame (e1, e2) of its
+// primitive at the current position:
+//   triangle: e1 = normalize(P1 - P0), n_g = normalize((P1-P0) x (P2-P0)),
+//             e2 = n_g x e1, x(a, b) = x_cur + a e1 + b e2 (exact, planar);
+//             shading normal = normalized barycentric blend of vertex normals;
+//   sphere:   n = (x_cur - c)/|x_cur - c|, (e1, e2) = onb(n),
+//             x(a, b) = c + r normalize(x_cur - c + a e1 + b e2), n_s = n_g = n.
+// ---------------------------------------------------------------------------
+struct VGeo {
+  int prim = 0, obj = 0, mat = 0;
+  bool sphere = false;
+  double ior = 1.0;
+  V3d x, e1, e2, ng;
+  V3d P0, N0, N1, N2;
+  double lenE1 = 1, E2e1 = 0, E2e2 = 1;
+  V3d c;
+  double r = 1;
+};
+
+static VGeo make_geo(const Scene& s, int prim, const V3d& x) {
+  VGeo g;
+  g.prim = prim;
+  g.obj = s.prim_obj(prim);
+  g.mat = s.mat[g.obj];
+  g.ior = s.ior[g.obj];
+  g.x = x;
+  if (prim < 0) {
+    int k = -1 - prim;
+    g.sphere = true;
+    g.c = s.sc[k];
+    g.r = s.sr[k];
+    g.ng = normalize(x - g.c);
+    onb(g.ng, &g.e1, &g.e2);
+    return g;
+  }
+  V3d a, b, c;
+  tri_verts(s, prim, &a, &b, &c);
+  V3d E1 = b - a, E2 = c - a;
+  g.P0 = a;
+  g.N0 = s.N[s.tri[3 * prim]];
+  g.N1 = s.N[s.tri[3 * prim + 1]];
+  g.N2 = s.N[s.tri[3 * prim + 2]];
+  g.lenE1 = norm(E1);
+  g.e1 = E1 * (1.0 / g.lenE1);
+  g.ng = normalize(cross(E1, E2));
+  g.e2 = cross(g.ng, g.e1);
+  g.E2e1 = dot(E2, g.e1);
+  g.E2e2 = dot(E2, g.e2);
+  return g;
+}
+
+template <class T>
+static V3<T> geo_pos(const VGeo& g, const T& a, const T& b) {
+  V3<T> off = lift<T>(g.e1) * a + lift<T>(g.e2) * b;
+  if (g.sphere) return lift<T>(g.c) + normalize(lift<T>(g.x - g.c) + off) * T(g.r);
+  return lift<T>(g.x) + off;
+}
+
+template <class T>
+static V3<T> geo_shading(const VGeo& g, const V3<T>& x) {
+  if (g.sphere) return normalize(x - lift<T>(g.c));
+  V3<T> q = x - lift<T>(g.P0);
+  T a = dot(q, lift<T>(g.e1)), b = dot(q, lift<T>(g.e2));
+  T b2 = b / T(g.E2e2);
+  T b1 = (a - b2 * T(g.E2e1)) / T(g.lenE1);
+  T b0 = T(1) - b1 - b2;
+  return normalize(lift<T>(g.N0) * b0 + lift<T>(g.N1) * b1 + lift<T>(g.N2) * b2);
+}
+
+// Per-vertex constraint: the generalized half vector
+//   h = eta_a w_i + eta_b w_o,   w_i -> x_{i-1}, w_o -> x_{i+1} (unit),
+// must be parallel to the shading normal n_s.  eta_a is the index of the
+// medium on w_i's side of the geometric surface and eta_b that of the other
+// side for a transmission; both are 1 for a reflection, where h reduces to
+// the ordinary half vector.  The two residual components are the projections
+// of h/|h| on the orthonormal shading tangent frame
+//   s = normalize(e1 - (e1.n_s) n_s),  t = n_s x s.
+template <class T>
+static void vertex_constraint(const V3<T>& xp, const V3<T>& x, const V3<T>& xn, const V3<T>& ns, const V3d& e1,
+                              double eta_a, double eta_b, T* C) {
+  V3<T> wi = normalize(xp - x), wo = normalize(xn - x);
+  V3<T> h = normalize(wi * T(eta_a) + wo * T(eta_b));
+  V3<T> E1 = lift<T>(e1);
+  V3<T> s = normalize(E1 - ns * dot(E1, ns));
+  V3<T> t = cross(ns, s);
+  C[0] = dot(h, s);
+  C[1] = dot(h, t);
+}
+
+// Indices of refraction on the two sides of vertex g for incoming w_i.
+static void etas(const VGeo& g, bool transmit, const V3d& wi, double* ea, double* eb) {
+  if (!transmit) { *ea = *eb = 1.0; return; }
+  if (dot(wi, g.ng) > 0.0) { *ea = 1.0; *eb = g.ior; }
+  else { *ea = g.ior; *eb = 1.0; }
+}
+
+struct Chain {
+  int n = 0, type = 0;
+  VGeo v[KMAX];
+  V3d xD, xL;
+  double ea[KMAX], eb[KMAX];
+  bool T(int i) const { return (type >> i) & 1; }
+};
+
+static void chain_etas(Chain* c) {
+  for (int i = 0; i < c->n; ++i) {
+    V3d xp = i == 0 ? c->xD : c->v[i - 1].x;
+    etas(c->v[i], c->T(i), normalize(xp - c->v[i].x), &c->ea[i], &c->eb[i]);
+  }
+}
+
+// Residual of the whole chain at offsets y (2n values) and a perturbation
+// (u1, u2) of x_L in a tangent plane (t1, t2): used with dual numbers for
+// the Jacobian and with doubles for the values.
+template <class T>
+static void chain_residual(const Chain& c, const T* y, const T& u1, const T& u2, const V3d& t1, const V3d& t2,
+                           T* C) {
+  V3<T> x[KMAX + 2], ns[KMAX];
+  x[0] = lift<T>(c.xD);
+  x[c.n + 1] = lift<T>(c.xL) + lift<T>(t1) * u1 + lift<T>(t2) * u2;
+  for (int i = 0; i < c.n; ++i) {
+    x[i + 1] = geo_pos(c.v[i], y[2 * i], y[2 * i + 1]);
+    ns[i] = geo_shading(c.v[i], x[i + 1]);
+  }
+  for (int i = 0; i < c.n; ++i)
+    vertex_constraint(x[i], x[i + 1], x[i + 2], ns[i], c.v[i].e1, c.ea[i], c.eb[i], &C[2 * i]);
+}
+
+static void residual(const Chain& c, double* C) {
+  double y[2 * KMAX] = {0};
+  chain_residual<double>(c, y, 0.0, 0.0, V3d(), V3d(), C);
+}
+
+typedef Dual<double, 2 * KMAX + 2> DJ;
+
+// Dense Jacobian J = dC/dy (2n x 2n) and B = dC/du_L (2n x 2) by forward-mode AD.
+static void jacobian(const Chain& c, const V3d& t1, const V3d& t2, double* C, double* J, double* B) {
+  const int m = 2 * c.n;
+  DJ y[2 * KMAX];
+  for (int k = 0; k < m; ++k) y[k] = DJ::var(0.0, k);
+  DJ u1 = DJ::var(0.0, 2 * KMAX), u2 = DJ::var(0.0, 2 * KMAX + 1);
+  DJ Cd[2 * KMAX];
+  chain_residual<DJ>(c, y, u1, u2, t1, t2, Cd);
+  for (int r = 0; r < m; ++r) {
+    if (C) C[r] = Cd[r].v;
+    for (int k = 0; k < m; ++k) J[r * m + k] = Cd[r].d[k];
+    if (B) {
+      B[r * 2] = Cd[r].d[2 * KMAX];
+      B[r * 2 + 1] = Cd[r].d[2 * KMAX + 1];
+    }
+  }
+}
+
+// Dense Gaussian elimination with partial pivoting; X (m x k) overwrites R.
+// Returns false when a pivot falls below 1e-14 of the largest entry of A.
+static bool dense_solve(int m, double* A, int k, double* R) {
+  double amax = 0.0;
+  for (int i = 0; i < m * m; ++i) amax = std::max(amax, std::fabs(A[i]));
+  if (!(amax > 0.0) || !std::isfinite(amax)) return false;
+  for (int col = 0; col < m; ++col) {
+    int p = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(A[r * m + col]) > std::fabs(A[p * m + col])) p = r;
+    if (std::fabs(A[p * m + col]) < 1e-14 * amax) return false;
+    if (p != col) {
+      for (int j = 0; j < m; ++j) std::swap(A[p * m + j], A[col * m + j]);
+      for (int j = 0; j < k; ++j) std::swap(R[p * k + j], R[col * k + j]);
+    }
+    for (int r = col + 1; r < m; ++r) {
+      double f = A[r * m + col] / A[col * m + col];
+      if (f == 0.0) continue;
+      for (int j = col; j < m; ++j) A[r * m + j] -= f * A[col * m + j];
+      for (int j = 0; j < k; ++j) R[r * k + j] -= f * R[col * k + j];
+    }
+  }
+  for (int col = m - 1; col >= 0; --col) {
+    for (int j = 0; j < k; ++j) {
+      double acc = R[col * k + j];
+      for (int c2 = col + 1; c2 < m; ++c2) acc -= A[col * m + c2] * R[c2 * k + j];
+      R[col * k + j] = acc / A[col * m + col];
+    }
+  }
+  return true;
+}
+
+static double inf_norm(const double* v, int m) {
+  double r = 0.0;
+  for (int i = 0; i < m; ++i) r = std::max(r, std::fabs(v[i]));
+  return r;
+}
+static double two_norm(const double* v, int m) {
+  double r = 0.0;
+  for (int i = 0; i < m; ++i) r += v[i] * v[i];
+  return std::sqrt(r);
+}
+
+struct Params {
+  int max_iter;
+  double tol_vertex;    // converged when the full Newton step moves every vertex <= tol_vertex * scale
+  double tol_residual;  // ... and the residual's max-norm after that step is <= tol_residual
+  double scale;         // scene scale L
+  double tmin_rel;      // ray epsilon, relative to L
+  double match_rel;     // trial-match distance, relative to L
+  double polish_tol;    // FP64 polish target (oracle only)
+  double cone_cos;      // direction-mode p_0: cosine of the cone half-angle about n_D
+};
+
+// Newton direction: solve J delta = -C; the 3-D displacement of vertex i is
+// delta_a e1 + delta_b e2.
+static bool newton_direction(const Chain& c, double* C, V3d* disp) {
+  const int m = 2 * c.n;
+  double J[4 * KMAX * KMAX], R[2 * KMAX];
+  jacobian(c, V3d(), V3d(), C, J, nullptr);
+  for (int i = 0; i < m; ++i) R[i] = -C[i];
+  if (!dense_solve(m, J, 1, R)) return false;
+  for (int i = 0; i < c.n; ++i) disp[i] = c.v[i].e1 * R[2 * i] + c.v[i].e2 * R[2 * i + 1];
+  return true;
+}
+
+// Reprojection: for i = 1..n in order, cast a ray from the (already moved)
+// previous vertex toward the displaced vertex i; the first hit over the whole
+// scene must lie on vertex i's object.  x_0 = x_D.
+static bool reproject(const Scene& s, const Chain& c, const V3d* target, double tmin, Chain* out) {
+  *out = c;
+  for (int i = 0; i < c.n; ++i) {
+    V3d o = i == 0 ? c.xD : out->v[i - 1].x;
+    int excl = i == 0 ? std::numeric_limits<int>::min() : out->v[i - 1].prim;
+    V3d dir = target[i] - o;
+    double len = norm(dir);
+    if (!(len > 0.0)) return false;
+    dir = dir * (1.0 / len);
+    Hit h = cast_ray(s, o, dir, excl, tmin);
+    if (!h.ok) return false;
+    if (s.prim_obj(h.prim) != c.v[i].obj) return false;
+    out->v[i] = make_geo(s, h.prim, o + dir * h.t);
+  }
+  chain_etas(out);
+  return true;
+}
+
+struct WalkResult {
+  int8_t status = ST_BAD_INPUT;
+  int iters = 0;
+  int polish_steps = 0;
+  bool polished = false;
+  double residual = 0;
+  double G = 0, kappa = 0;
+  uint64_t sol = 0;
+  Chain chain;
+};
+
+// Manifold walk (Sec. 3): Newton's method with reprojection and the
+// step-length rule below (the paper leaves the rule to its citations):
+//   beta = 1; every trial step counts as one iteration;
+//   trial x' = reproject(x + beta delta); a failed reprojection halves beta;
+//   converged when beta == 1, max_i |delta_i| <= tol_vertex L and
+//   |C(x')|_inf <= tol_residual (x' is kept);
+//   otherwise accept iff |C(x')|_2 < |C(x)|_2 (then beta = min(1, 2 beta)),
+//   else halve beta.
+static void walk_core(const Scene& s, const Params& p, const Chain& start, WalkResult* res) {
+  const int m = 2 * start.n;
+  const double tmin = p.tmin_rel * p.scale;
+  Chain c = start;
+  double C[2 * KMAX];
+  V3d disp[KMAX];
+  if (!newton_direction(c, C, disp)) { res->status = ST_SINGULAR; res->chain = c; return; }
+  double beta = 1.0;
+  res->status = ST_MAX_ITER;
+  for (int it = 1; it <= p.max_iter; ++it) {
+    res->iters = it;
+    double step = 0.0;
+    V3d target[KMAX];
+    for (int i = 0; i < c.n; ++i) {
+      step = std::max(step, norm(disp[i]));
+      target[i] = c.v[i].x + disp[i] * beta;
+    }
+    Chain trial;
+    if (!reproject(s, c, target, tmin, &trial)) { beta *= 0.5; continue; }
+    double Ct[2 * KMAX];
+    residual(trial, Ct);
+    if (beta == 1.0 && step <= p.tol_vertex * p.scale && inf_norm(Ct, m) <= p.tol_residual) {
+      c = trial;
+      res->status = ST_CONVERGED;
+      break;
+    }
+    if (two_norm(Ct, m) < two_norm(C, m)) {
+      c = trial;
+      if (!newton_direction(c, C, disp)) { res->status = ST_SINGULAR; break; }
+      beta = std::min(1.0, 2.0 * beta);
+    } else {
+      beta *= 0.5;
+    }
+  }
+  res->chain = c;
+}
+
+// Oracle-only FP64 polish: pure Newton steps (beta = 1) with reprojection.
+static void polish(const Scene& s, const Params& p, WalkResult* res) {
+  Chain& c = res->chain;
+  const int m = 2 * c.n;
+  double C[2 * KMAX];
+  residual(c, C);
+  for (int k = 0; k < 10 && inf_norm(C, m) >= p.polish_tol; ++k) {
+    V3d disp[KMAX], target[KMAX];
+    double Cn[2 * KMAX];
+    if (!newton_direction(c, Cn, disp)) break;
+    for (int i = 0; i < c.n; ++i) target[i] = c.v[i].x + disp[i];
+    Chain t;
+    if (!reproject(s, c, target, p.tmin_rel * p.scale, &t)) break;
+    double Ct[2 * KMAX];
+    residual(t, Ct);
+    if (!(inf_norm(Ct, m) < inf_norm(C, m))) break;
+    c = t;
+    std::memcpy(C, Ct, sizeof(double) * m);
+    res->polish_steps++;
+  }
+  res->residual = inf_norm(C, m);
+  res->polished = res->residual < 1e-10;
+}
+
+// Unpolarized Fresnel reflectance of a smooth dielectric interface (textbook
+// exact form): cos_i on the incident side, eta_i / eta_t the index ratio.
+static double fresnel_dielectric(double cos_i, double eta_i, double eta_t) {
+  cos_i = std::fabs(cos_i);
+  double e = eta_i / eta_t;
+  double sin2_t = e * e * std::max(0.0, 1.0 - cos_i * cos_i);
+  if (sin2_t >= 1.0) return 1.0;
+  double cos_t = std::sqrt(1.0 - sin2_t);
+  double rs = (eta_i * cos_i - eta_t * cos_t) / (eta_i * cos_i + eta_t * cos_t);
+  double rp = (eta_t * cos_i - eta_i * cos_t) / (eta_t * cos_i + eta_i * cos_t);
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+// kappa of Eq. (ThroughputEval): product of the per-vertex scattering
+// coefficients (ideal mirror 1, dielectric reflection F, transmission 1 - F).
+static double chain_kappa(const Chain& c) {
+  double k = 1.0;
+  for (int i = 0; i < c.n; ++i) {
+    const VGeo& g = c.v[i];
+    if (g.mat == MAT_MIRROR) continue;
+    V3d xp = i == 0 ? c.xD : c.v[i - 1].x;
+    V3d wi = normalize(xp - g.x);
+    V3d ns = geo_shading<double>(g, g.x);
+    double F = fresnel_dielectric(dot(wi, ns), c.ea[i], c.T(i) ? c.eb[i] : c.ea[i]);
+    k *= c.T(i) ? (1.0 - F) : F;
+  }
+  return k;
+}
+
+// Generalized geometric term (Eq. ThroughputEval; it maps the differential
+// area at x_L to the projected solid angle at x_D):
+//   G = |n_D . w_D| * |d w_D / d A_L|,
+// with d x_1 / d x_L from the implicit function theorem on the constraint
+// (dy/du_L = -J^{-1} dC/du_L, only the last block row of dC/du_L is nonzero)
+// and x_L's area element taken in the plane perpendicular to x_n - x_L
+// (point lights).  For n = 0 it reduces to |cos_D| |cos_L| / d^2.
+static double chain_G(const Chain& c, const V3d& nD) {
+  const int m = 2 * c.n;
+  V3d wl = normalize(c.v[c.n - 1].x - c.xL);
+  V3d t1, t2;
+  onb(wl, &t1, &t2);
+  double J[4 * KMAX * KMAX], B[4 * KMAX];
+  jacobian(c, t1, t2, nullptr, J, B);
+  for (int i = 0; i < 2 * m; ++i) B[i] = -B[i];
+  if (!dense_solve(m, J, 2, B)) return 0.0;
+  V3d dx[2];
+  for (int k = 0; k < 2; ++k) dx[k] = c.v[0].e1 * B[0 * 2 + k] + c.v[0].e2 * B[1 * 2 + k];
+  V3d d = c.v[0].x - c.xD;
+  double len = norm(d);
+  V3d w = d * (1.0 / len);
+  V3d dw[2];
+  for (int k = 0; k < 2; ++k) dw[k] = (dx[k] - w * dot(w, dx[k])) * (1.0 / len);
+  double area = std::fabs(dot(w, cross(dw[0], dw[1])));
+  return std::fabs(dot(nD, w)) * area;
+}
+
+static bool side_ok(const Chain& c) {
+  for (int i = 0; i < c.n; ++i) {
+    V3d xp = i == 0 ? c.xD : c.v[i - 1].x;
+    V3d xn = i == c.n - 1 ? c.xL : c.v[i + 1].x;
+    double a = dot(xp - c.v[i].x, c.v[i].ng), b = dot(xn - c.v[i].x, c.v[i].ng);
+    if (c.T(i) ? !(a * b < 0.0) : !(a * b > 0.0)) return false;
+  }
+  return true;
+}
+
+static bool visible_to_light(const Scene& s, const Params& p, const Chain& c) {
+  const VGeo& last = c.v[c.n - 1];
+  V3d d = c.xL - last.x;
+  double dist = norm(d);
+  Hit h = cast_ray(s, last.x, d * (1.0 / dist), last.prim, p.tmin_rel * p.scale);
+  return !(h.ok && h.t < dist * (1.0 - 1e-9));
+}
+
+static bool load_chain(const Scene& s, int n, int type, const V3d& xD, const V3d& xL, const int* prim,
+                       const V3d* pos, Chain* c) {
+  if (n < 1 || n > KMAX) return false;
+  c->n = n;
+  c->type = type;
+  c->xD = xD;
+  c->xL = xL;
+  for (int i = 0; i < n; ++i) {
+    if (prim[i] >= s.ntri() || (prim[i] < 0 && -1 - prim[i] >= (int)s.sr.size())) return false;
+    c->v[i] = make_geo(s, prim[i], pos[i]);
+    if (c->T(i) && c->v[i].mat != MAT_DIELECTRIC) return false;
+  }
+  chain_etas(c);
+  return true;
+}
+
+static bool finite3(const V3d& v) { return std::isfinite(v.x) && std::isfinite(v.y) && std::isfinite(v.z); }
+
+// Full walk of one chain: walk, (oracle) polish, side and visibility tests,
+// then G, kappa and the solution id.
+static void walk_chain(const Scene& s, const Params& p, int n, int type, const V3d& xD, const V3d& nD, const V3d& xL,
+                       const int* prim, const V3d* pos, bool do_polish, WalkResult* res) {
+  Chain c;
+  if (!finite3(xD) || !finite3(xL) || n < 1 || n > KMAX) { res->status = ST_BAD_INPUT; return; }
+  if (!load_chain(s, n, type, xD, xL, prim, pos, &c)) { res->status = ST_SEED_INVALID; res->chain = c; return; }
+  walk_core(s, p, c, res);
+  if (res->status != ST_CONVERGED) return;
+  if (do_polish) polish(s, p, res);
+  else {
+    double C[2 * KMAX];
+    residual(res->chain, C);
+    res->residual = inf_norm(C, 2 * n);
+  }
+  if (!side_ok(res->chain)) { res->status = ST_SIDE_INVALID; return; }
+  if (!visible_to_light(s, p, res->chain)) { res->status = ST_OCCLUDED; return; }
+  res->kappa = chain_kappa(res->chain);
+  res->G = chain_G(res->chain, nD);
+  int prims[KMAX];
+  for (int i = 0; i < n; ++i) prims[i] = res->chain.v[i].prim;
+  res->sol = solution_id(n, type, prims);
+}
+
+// ---------------------------------------------------------------------------
+// Seeds: p_0 (Sec. 5.4), the guided 2-D Gaussian mixture, the defensive
+// one-sample mixture of the two (Sec. 5.5), and deduction (Eq. deduction).
+// ---------------------------------------------------------------------------
+struct Guide {
+  int res = 32, comps = 8;
+  double lo[3], hi[3];
+  int target_obj = 0;
+  std::vector<int> valid;      // [cells]
+  std::vector<double> pi;      // [cells][comps]
+  std::vector<double> mu;      // [cells][comps][2]
+  std::vector<double> chol;    // [cells][comps][3]  L00, L10, L11
+};
+
+static int guide_cell(const Guide& g, const V3d& x) {
+  int idx[3];
+  for (int a = 0; a < 3; ++a) {
+    double f = (x[a] - g.lo[a]) / (g.hi[a] - g.lo[a]) * g.res;
+    int k = (int)std::floor(f);
+    if (!(f == f)) return -1;
+    idx[a] = std::min(std::max(k, 0), g.res - 1);
+  }
+  return (idx[2] * g.res + idx[1]) * g.res + idx[0];
+}
+
+// p_0 (Sec. 5.4).  obj1 >= 0: x_1 uniform by area on that object;
+// obj1 == -1: uniform by area over all specular objects; for an analytic
+// sphere the point is uniform over the cap visible from x_D.  obj1 == -2:
+// the direction-based initialization (Sec. 7, "Initialization"): w_D uniform
+// in the cone of directions about n_D with cos(half-angle) = cone_cos.
+static bool sample_p0_point(const Scene& s, const Params& p, int obj1, const V3d& xD, const V3d& nD, double u1,
+                            double u2, double u3, V3d* pt) {
+  if (obj1 == -2) {
+    V3d ax = normalize(nD), b1, b2;
+    onb(ax, &b1, &b2);
+    double ct = 1.0 - u2 * (1.0 - p.cone_cos);
+    double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+    double ph = 2.0 * kPi * u3;
+    *pt = xD + b1 * (st * std::cos(ph)) + b2 * (st * std::sin(ph)) + ax * ct;
+    return true;
+  }
+  (void)u1;
+  int key = obj1 < 0 ? s.nobj() : obj1;
+  if (key > s.nobj()) return false;
+  const std::vector<double>& cdf = s.cdf[key];
+  if (cdf.empty() || !(cdf.back() > 0.0)) return false;
+  double target = u1 * cdf.back();
+  size_t j = std::upper_bound(cdf.begin(), cdf.end(), target) - cdf.begin();
+  if (j >= cdf.size()) j = cdf.size() - 1;
+  int prim = s.cdf_prim[key][j];
+  if (prim >= 0) {
+    V3d a, b, c;
+    tri_verts(s, prim, &a, &b, &c);
+    double r = std::sqrt(u2);
+    *pt = a * (1.0 - r) + b * (r * (1.0 - u3)) + c * (r * u3);
+    return true;
+  }
+  // sphere: uniform over the cap visible from x_D
+  int k = -1 - prim;
+  V3d oc = xD - s.sc[k];
+  double d = norm(oc);
+  if (!(d > s.sr[k])) return false;
+  V3d ax = oc * (1.0 / d), b1, b2;
+  onb(ax, &b1, &b2);
+  double cmax = s.sr[k] / d;
+  double ct = 1.0 - u2 * (1.0 - cmax);
+  double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  double ph = 2.0 * kPi * u3;
+  *pt = s.sc[k] + (b1 * (st * std::cos(ph)) + b2 * (st * std::sin(ph)) + ax * ct) * s.sr[k];
+  return true;
+}
+
+static bool sample_guided_point(const Scene& s, const Guide& g, int cell, uint64_t seed, uint64_t chain,
+                                uint64_t trial, const Uniforms& U0, V3d* pt) {
+  const int K = g.comps;
+  for (int attempt = 0; attempt <= 8; ++attempt) {
+    Uniforms U = attempt == 0 ? U0 : draw(seed, chain, trial, attempt);
+    double acc = 0.0;
+    int j = K - 1;
+    for (int q = 0; q < K; ++q) {
+      acc += g.pi[cell * K + q];
+      if (U.u[1] < acc) { j = q; break; }
+    }
+    double rr = std::sqrt(-2.0 * std::log(1.0 - U.u[2]));
+    double z0 = rr * std::cos(2.0 * kPi * U.u[3]), z1 = rr * std::sin(2.0 * kPi * U.u[3]);
+    const double* mu = &g.mu[(cell * K + j) * 2];
+    const double* L = &g.chol[(cell * K + j) * 3];
+    double px = mu[0] + L[0] * z0, py = mu[1] + L[1] * z0 + L[2] * z1;
+    int o = g.target_obj;
+    if (px < s.obj_lo_x[o] || px > s.obj_hi_x[o] || py < s.obj_lo_y[o] || py > s.obj_hi_y[o]) continue;
+    // lift onto the surface with a vertical ray from above the scene
+    Hit h = cast_ray(s, V3d(px, py, s.zmax + 1.0), V3d(0, 0, -1), std::numeric_limits<int>::min(), 0.0);
+    if (!h.ok) return false;
+    *pt = V3d(px, py, s.zmax + 1.0 - h.t);
+    return true;
+  }
+  return false;
+}
+
+static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n, int type, int obj1,
+                          const V3d& xD, const V3d& nD, uint64_t seed, uint64_t chain, uint64_t trial, double alpha,
+                          int* prim, V3d* pos) {
+  if (n < 1 || n > KMAX || !finite3(xD)) return ST_BAD_INPUT;
+  Uniforms U = draw(seed, chain, trial, 0);
+  V3d pt;
+  bool ok;
+  int cell = g ? guide_cell(*g, xD) : -1;
+  bool guided = g && cell >= 0 && g->valid[cell] && !(U.u[0] < alpha);
+  if (guided) {
+    ok = sample_guided_point(s, *g, cell, seed, chain, trial, U, &pt);
+    if (!ok) ok = sample_p0_point(s, p, obj1, xD, nD, U.u[1], U.u[2], U.u[3], &pt);
+  } else {
+    ok = sample_p0_point(s, p, obj1, xD, nD, U.u[1], U.u[2], U.u[3], &pt);
+  }
+  if (!ok) return ST_SEED_INVALID;
+  const double tmin = p.tmin_rel * p.scale;
+  V3d o = xD, d = pt - xD;
+  double len = norm(d);
+  if (!(len > 0.0)) return ST_SEED_INVALID;
+  d = d * (1.0 / len);
+  int excl = std::numeric_limits<int>::min();
+  for (int i = 0; i < n; ++i) {
+    if (i > 0) {
+      // scatter at vertex i-1 with its type (Eq. deduction)
+      VGeo gv = make_geo(s, prim[i - 1], pos[i - 1]);
+      V3d ns = geo_shading<double>(gv, gv.x);
+      if ((type >> (i - 1)) & 1) {
+        if (gv.mat != MAT_DIELECTRIC) return ST_SEED_INVALID;
+        bool entering = dot(d, gv.ng) < 0.0;
+        double eta = entering ? 1.0 / gv.ior : gv.ior;
+        V3d nn = entering ? ns : -ns;
+        double ci = -dot(d, nn);
+        if (!(ci > 0.0)) return ST_SEED_INVALID;
+        double s2 = eta * eta * (1.0 - ci * ci);
+        if (s2 >= 1.0) return ST_SEED_INVALID;
+        d = normalize(d * eta + nn * (eta * ci - std::sqrt(1.0 - s2)));
+      } else {
+        d = normalize(d - ns * (2.0 * dot(d, ns)));
+      }
+      o = pos[i - 1];
+      excl = prim[i - 1];
+    }
+    Hit h = cast_ray(s, o, d, excl, tmin);
+    if (!h.ok) return ST_SEED_INVALID;
+    prim[i] = h.prim;
+    pos[i] = o + d * h.t;
+  }
+  for (int i = 0; i < n; ++i)
+    if (((type >> i) & 1) && s.mat[s.prim_obj(prim[i])] != MAT_DIELECTRIC) return ST_SEED_INVALID;
+  return ST_CONVERGED;  // 0: valid seed
+}
+
+static bool chains_match(const Scene& s, const Chain& a, const Chain& b, double tol) {
+  if (a.n != b.n || a.type != b.type) return false;
+  for (int i = 0; i < a.n; ++i) {
+    if (s.prim_obj(a.v[i].prim) != s.prim_obj(b.v[i].prim)) return false;
+    if (norm(a.v[i].x - b.v[i].x) > tol) return false;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Weighted EM for a 2-D Gaussian mixture per spatial cell (the guide's
+// directional stand-in).  Standard EM (Dempster, Laird, Rubin 1977) with
+// per-sample weights w = T <1/P> (Eq. eq_weight).
+// ---------------------------------------------------------------------------
+struct EMParams {
+  int res, comps, iters, min_samples;
+  double lo[3], hi[3];
+  double reg;  // added to the covariance diagonal
+};
+
+static void em_cell(const EMParams& ep, const std::vector<int>& idx, const float* samples, int* valid, double* pi,
+                    double* mu, double* cov) {
+  const int K = ep.comps;
+  const int m = (int)idx.size();
+  *valid = 0;
+  for (int j = 0; j < K; ++j) {
+    pi[j] = 0.0;
+    mu[2 * j] = mu[2 * j + 1] = 0.0;
+    cov[3 * j] = cov[3 * j + 2] = 1.0;
+    cov[3 * j + 1] = 0.0;
+  }
+  if (m < ep.min_samples) return;
+  std::vector<double> X(2 * m), W(m);
+  double Wt = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const float* r = samples + 8 * (size_t)idx[i];
+    X[2 * i] = r[3];
+    X[2 * i + 1] = r[4];
+    W[i] = r[5];
+    Wt += W[i];
+  }
+  if (!(Wt > 0.0)) return;
+  double mx = 0, my = 0;
+  for (int i = 0; i < m; ++i) { mx += W[i] * X[2 * i]; my += W[i] * X[2 * i + 1]; }
+  mx /= Wt; my /= Wt;
+  double sxx = 0, sxy = 0, syy = 0;
+  for (int i = 0; i < m; ++i) {
+    double dx = X[2 * i] - mx, dy = X[2 * i + 1] - my;
+    sxx += W[i] * dx * dx; sxy += W[i] * dx * dy; syy += W[i] * dy * dy;
+  }
+  sxx = sxx / Wt + ep.reg; sxy /= Wt; syy = syy / Wt + ep.reg;
+  for (int j = 0; j < K; ++j) {
+    int s = (int)std::floor((j + 0.5) * m / K);
+    pi[j] = 1.0 / K;
+    mu[2 * j] = X[2 * s];
+    mu[2 * j + 1] = X[2 * s + 1];
+    cov[3 * j] = sxx; cov[3 * j + 1] = sxy; cov[3 * j + 2] = syy;
+  }
+  std::vector<double> R((size_t)m * K);
+  for (int it = 0; it < ep.iters; ++it) {
+    // E step: responsibilities under the current parameters
+    for (int i = 0; i < m; ++i) {
+      double lp[8], best = -kInf;
+      for (int j = 0; j < K; ++j) {
+        lp[j] = -kInf;
+        if (!(pi[j] > 0.0)) continue;
+        double a = cov[3 * j], b = cov[3 * j + 1], c = cov[3 * j + 2];
+        double det = a * c - b * b;
+        double dx = X[2 * i] - mu[2 * j], dy = X[2 * i + 1] - mu[2 * j + 1];
+        double q = (c * dx * dx - 2.0 * b * dx * dy + a * dy * dy) / det;
+        lp[j] = std::log(pi[j]) - 0.5 * q - 0.5 * std::log(det);
+        best = std::max(best, lp[j]);
+      }
+      double z = 0.0;
+      for (int j = 0; j < K; ++j) z += lp[j] == -kInf ? 0.0 : std::exp(lp[j] - best);
+      for (int j = 0; j < K; ++j) R[(size_t)i * K + j] = lp[j] == -kInf ? 0.0 : std::exp(lp[j] - best) / z;
+    }
+    // M step: weighted counts, means, then covariances about the new means
+    for (int j = 0; j < K; ++j) {
+      double Nj = 0.0, sx = 0.0, sy = 0.0;
+      for (int i = 0; i < m; ++i) {
+        double r = W[i] * R[(size_t)i * K + j];
+        Nj += r; sx += r * X[2 * i]; sy += r * X[2 * i + 1];
+      }
+      if (!(Nj > 1e-8 * Wt)) { pi[j] = 0.0; continue; }
+      double ux = sx / Nj, uy = sy / Nj;
+      double cxx = 0.0, cxy = 0.0, cyy = 0.0;
+      for (int i = 0; i < m; ++i) {
+        double r = W[i] * R[(size_t)i * K + j];
+        double dx = X[2 * i] - ux, dy = X[2 * i + 1] - uy;
+        cxx += r * dx * dx; cxy += r * dx * dy; cyy += r * dy * dy;
+      }
+      pi[j] = Nj / Wt;
+      mu[2 * j] = ux; mu[2 * j + 1] = uy;
+      cov[3 * j] = cxx / Nj + ep.reg; cov[3 * j + 1] = cxy / Nj; cov[3 * j + 2] = cyy / Nj + ep.reg;
+    }
+  }
+  *valid = 1;
+}
+
+static int em_cell_index(const EMParams& ep, const float* r) {
+  int idx[3];
+  for (int a = 0; a < 3; ++a) {
+    double f = ((double)r[a] - ep.lo[a]) / (ep.hi[a] - ep.lo[a]) * ep.res;
+    if (!(f == f)) return -1;
+    int k = (int)std::floor(f);
+    idx[a] = std::min(std::max(k, 0), ep.res - 1);
+  }
+  return (idx[2] * ep.res + idx[1]) * ep.res + idx[0];
+}
+
+// ---------------------------------------------------------------------------
+// threads
+// ---------------------------------------------------------------------------
+template <class F>
+static void parallel_for(int n, int nthreads, F fn) {
+  if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
+  nthreads = std::max(1, std::min(nthreads, n));
+  if (nthreads == 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&]() {
+      for (;;) {
+        int i0 = next.fetch_add(16);
+        if (i0 >= n) break;
+        for (int i = i0; i < std::min(n, i0 + 16); ++i) fn(i);
+      }
+    });
+  for (auto& th : pool) th.join();
+}
+
+static V3d get3d(const double* a, int n, int i) { return V3d(a[i], a[n + i], a[2 * n + i]); }
+
+}  // namespace oracle
+
+using namespace oracle;
+
+// ---------------------------------------------------------------------------
+// C interface (ctypes)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+struct orc_params {
+  int32_t max_iter;
+  double tol_vertex, tol_residual, scale, tmin_rel, match_rel, polish_tol, cone_cos;
+};
+
+void* orc_scene_create(int nv, const float* verts, const float* normals, int nt, const int32_t* tris,
+                       const int32_t* tri_obj, int nobj, const int32_t* mat, const float* ior, int ns,
+                       const float* spheres, const int32_t* sphere_obj, double scale) {
+  Scene* s = new Scene();
+  s->P.resize(nv);
+  s->N.resize(nv);
+  for (int i = 0; i < nv; ++i) {
+    s->P[i] = V3d(verts[3 * i], verts[3 * i + 1], verts[3 * i + 2]);
+    s->N[i] = normalize(V3d(normals[3 * i], normals[3 * i + 1], normals[3 * i + 2]));
+  }
+  s->tri.assign(tris, tris + 3 * nt);
+  s->tri_obj.assign(tri_obj, tri_obj + nt);
+  s->mat.assign(mat, mat + nobj);
+  s->ior.resize(nobj);
+  for (int i = 0; i < nobj; ++i) s->ior[i] = ior[i];
+  for (int k = 0; k < ns; ++k) {
+    s->sc.push_back(V3d(spheres[4 * k], spheres[4 * k + 1], spheres[4 * k + 2]));
+    s->sr.push_back(spheres[4 * k + 3]);
+    s->sobj.push_back(sphere_obj[k]);
+  }
+  s->scale = scale;
+  if (nt > 0) {
+    std::vector<V3d> cen(nt);
+    for (int t = 0; t < nt; ++t) {
+      V3d a, b, c;
+      tri_verts(*s, t, &a, &b, &c);
+      cen[t] = (a + b + c) * (1.0 / 3.0);
+    }
+    s->order.resize(nt);
+    for (int t = 0; t < nt; ++t) s->order[t] = t;
+    build_node(*s, cen, 0, nt);
+  }
+  // area CDFs per object and over all objects; xy bounds per object
+  s->cdf.assign(nobj + 1, {});
+  s->cdf_prim.assign(nobj + 1, {});
+  s->obj_lo_x.assign(nobj, kInf); s->obj_lo_y.assign(nobj, kInf);
+  s->obj_hi_x.assign(nobj, -kInf); s->obj_hi_y.assign(nobj, -kInf);
+  s->zmax = -kInf;
+  auto add = [&](int key, int prim, double area) {
+    double prev = s->cdf[key].empty() ? 0.0 : s->cdf[key].back();
+    s->cdf[key].push_back(prev + area);
+    s->cdf_prim[key].push_back(prim);
+  };
+  for (int t = 0; t < nt; ++t) {
+    V3d a, b, c;
+    tri_verts(*s, t, &a, &b, &c);
+    double area = 0.5 * norm(cross(b - a, c - a));
+    add(s->tri_obj[t], t, area);
+    add(nobj, t, area);
+    int o = s->tri_obj[t];
+    for (const V3d* v : {&a, &b, &c}) {
+      s->obj_lo_x[o] = std::min(s->obj_lo_x[o], v->x); s->obj_hi_x[o] = std::max(s->obj_hi_x[o], v->x);
+      s->obj_lo_y[o] = std::min(s->obj_lo_y[o], v->y); s->obj_hi_y[o] = std::max(s->obj_hi_y[o], v->y);
+      s->zmax = std::max(s->zmax, v->z);
+    }
+  }
+  for (int k = 0; k < ns; ++k) {
+    double area = 4.0 * kPi * s->sr[k] * s->sr[k];
+    add(s->sobj[k], -1 - k, area);
+    add(nobj, -1 - k, area);
+    int o = s->sobj[k];
+    s->obj_lo_x[o] = std::min(s->obj_lo_x[o], s->sc[k].x - s->sr[k]);
+    s->obj_hi_x[o] = std::max(s->obj_hi_x[o], s->sc[k].x + s->sr[k]);
+    s->obj_lo_y[o] = std::min(s->obj_lo_y[o], s->sc[k].y - s->sr[k]);
+    s->obj_hi_y[o] = std::max(s->obj_hi_y[o], s->sc[k].y + s->sr[k]);
+    s->zmax = std::max(s->zmax, s->sc[k].z + s->sr[k]);
+  }
+  return s;
+}
+
+void orc_scene_destroy(void* s) { delete (Scene*)s; }
+
+int orc_scene_set_heightfield(void* sp, int obj, int res, int first_vert, int first_tri, double x0, double x1,
+                              double y0, double y1, double z0, int n_sines, const double* amp, const double* freq,
+                              const double* psi, const double* phase) {
+  Scene* s = (Scene*)sp;
+  if (n_sines > 8) return -1;
+  HeightField h;
+  h.obj = obj; h.res = res; h.first_vert = first_vert; h.first_tri = first_tri; h.n_sines = n_sines;
+  h.x0 = x0; h.x1 = x1; h.y0 = y0; h.y1 = y1; h.z0 = z0;
+  for (int k = 0; k < n_sines; ++k) { h.amp[k] = amp[k]; h.freq[k] = freq[k]; h.psi[k] = psi[k]; h.phase[k] = phase[k]; }
+  s->hfs.push_back(h);
+  return 0;
+}
+
+void orc_philox(uint64_t seed, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k1, uint64_t* out) {
+  uint64_t ctr[4] = {c0, c1, c2, c3};
+  uint64_t key[2] = {seed, k1};
+  philox4x64_10(ctr, key, out);
+}
+
+void orc_uniforms(uint64_t seed, uint64_t chain, uint64_t trial, uint64_t attempt, double* out) {
+  Uniforms U = draw(seed, chain, trial, attempt);
+  for (int j = 0; j < 8; ++j) out[j] = U.u[j];
+}
+
+uint64_t orc_solution_id(int n, int type, const int32_t* prim) { return solution_id(n, type, prim); }
+
+void orc_raycast(void* sp, int n, const double* o, const double* d, const int32_t* exclude, double tmin, int brute,
+                 int32_t* prim, double* t, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  parallel_for(n, nthreads, [&](int i) {
+    Hit h = cast_ray(s, V3d(o[3 * i], o[3 * i + 1], o[3 * i + 2]), V3d(d[3 * i], d[3 * i + 1], d[3 * i + 2]),
+                     exclude[i], tmin, brute != 0);
+    prim[i] = h.ok ? h.prim : INT32_MIN;
+    t[i] = h.ok ? h.t : kInf;
+  });
+}
+
+// Residual and dense Jacobian of one chain at given primitives / positions.
+int orc_constraint(void* sp, int n, int type, const double* xD, const double* xL, const int32_t* prim,
+                   const double* pos, double* C, double* J, double* frames) {
+  const Scene& s = *(Scene*)sp;
+  Chain c;
+  V3d p[KMAX];
+  for (int i = 0; i < n; ++i) p[i] = V3d(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+  if (!load_chain(s, n, type, V3d(xD[0], xD[1], xD[2]), V3d(xL[0], xL[1], xL[2]), prim, p, &c)) return -1;
+  jacobian(c, V3d(), V3d(), C, J, nullptr);
+  if (frames)
+    for (int i = 0; i < n; ++i) {
+      frames[6 * i + 0] = c.v[i].e1.x; frames[6 * i + 1] = c.v[i].e1.y; frames[6 * i + 2] = c.v[i].e1.z;
+      frames[6 * i + 3] = c.v[i].e2.x; frames[6 * i + 4] = c.v[i].e2.y; frames[6 * i + 5] = c.v[i].e2.z;
+    }
+  return 0;
+}
+
+// Positions of a chain moved by local offsets y (2n) -- for finite differences.
+int orc_offset_positions(void* sp, int n, const int32_t* prim, const double* pos, const double* y, double* out) {
+  const Scene& s = *(Scene*)sp;
+  for (int i = 0; i < n; ++i) {
+    VGeo g = make_geo(s, prim[i], V3d(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]));
+    V3d x = geo_pos<double>(g, y[2 * i], y[2 * i + 1]);
+    out[3 * i] = x.x; out[3 * i + 1] = x.y; out[3 * i + 2] = x.z;
+  }
+  return 0;
+}
+
+static const Guide* make_guide_view(const int32_t* gi, const double* gd, Guide* g) {
+  if (!gi) return nullptr;
+  // gi: res, comps, target_obj, valid[cells];  gd: lo[3], hi[3], pi, mu, chol
+  g->res = gi[0];
+  g->comps = gi[1];
+  g->target_obj = gi[2];
+  int cells = g->res * g->res * g->res;
+  g->valid.assign(gi + 3, gi + 3 + cells);
+  for (int a = 0; a < 3; ++a) { g->lo[a] = gd[a]; g->hi[a] = gd[3 + a]; }
+  const double* q = gd + 6;
+  g->pi.assign(q, q + (size_t)cells * g->comps); q += (size_t)cells * g->comps;
+  g->mu.assign(q, q + (size_t)cells * g->comps * 2); q += (size_t)cells * g->comps * 2;
+  g->chol.assign(q, q + (size_t)cells * g->comps * 3);
+  return g;
+}
+
+static Params to_params(const orc_params* p) {
+  Params q;
+  q.max_iter = p->max_iter; q.tol_vertex = p->tol_vertex; q.tol_residual = p->tol_residual;
+  q.scale = p->scale; q.tmin_rel = p->tmin_rel; q.match_rel = p->match_rel; q.polish_tol = p->polish_tol;
+  q.cone_cos = p->cone_cos;
+  return q;
+}
+
+void orc_sample_seeds(void* sp, const int32_t* gi, const double* gd, const orc_params* pp, int N, const double* xD,
+                      const double* nD, const uint8_t* len, const uint8_t* type, const int32_t* obj1, uint64_t seed, uint64_t trial,
+                      double alpha, int32_t* prim_out, double* pos_out, int8_t* status, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  Guide gstore;
+  const Guide* g = make_guide_view(gi, gd, &gstore);
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    int prim[KMAX];
+    V3d pos[KMAX];
+    for (int i = 0; i < KMAX; ++i) { prim[i] = INT32_MIN; pos[i] = V3d(); }
+    int8_t st = sample_seed(s, g, p, len[c], type[c], obj1[c], get3d(xD, N, c), get3d(nD, N, c), seed,
+                            (uint64_t)c, trial, alpha, prim, pos);
+    status[c] = st;
+    for (int i = 0; i < KMAX; ++i) {
+      prim_out[(size_t)i * N + c] = st == 0 ? prim[i] : INT32_MIN;
+      for (int a = 0; a < 3; ++a) pos_out[((size_t)a * KMAX + i) * N + c] = st == 0 ? pos[i][a] : 0.0;
+    }
+  });
+}
+
+void orc_walk(void* sp, const orc_params* pp, int N, const double* xD, const double* nD, const double* xL,
+              const uint8_t* len, const uint8_t* type, const int32_t* seed_prim, const float* seed_pos,
+              const int8_t* seed_status, int do_polish, int32_t* prim_out, double* pos_out, int8_t* status,
+              int32_t* iters, uint64_t* sol, double* G, double* kappa, double* resid, int8_t* polished,
+              int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    int n = len[c];
+    int prim[KMAX];
+    V3d pos[KMAX];
+    for (int i = 0; i < KMAX && i < n; ++i) {
+      prim[i] = seed_prim[(size_t)i * N + c];
+      pos[i] = V3d(seed_pos[((size_t)0 * KMAX + i) * N + c], seed_pos[((size_t)1 * KMAX + i) * N + c],
+                   seed_pos[((size_t)2 * KMAX + i) * N + c]);
+    }
+    WalkResult r;
+    if (seed_status && seed_status[c] != 0) r.status = ST_SEED_INVALID;
+    else walk_chain(s, p, n, type[c], get3d(xD, N, c), get3d(nD, N, c), get3d(xL, N, c), prim, pos,
+                    do_polish != 0, &r);
+    status[c] = r.status;
+    iters[c] = r.iters;
+    sol[c] = r.status == ST_CONVERGED ? r.sol : 0;
+    G[c] = r.G;
+    kappa[c] = r.kappa;
+    resid[c] = r.residual;
+    polished[c] = r.polished ? 1 : 0;
+    for (int i = 0; i < KMAX; ++i) {
+      bool have = i < n && i < r.chain.n && r.status != ST_BAD_INPUT && r.status != ST_SEED_INVALID;
+      prim_out[(size_t)i * N + c] = have ? r.chain.v[i].prim : INT32_MIN;
+      for (int a = 0; a < 3; ++a) pos_out[((size_t)a * KMAX + i) * N + c] = have ? r.chain.v[i].x[a] : 0.0;
+    }
+  });
+}
+
+// Reciprocal probability by repeated independent trials (Sec. 5.8): for a
+// converged target, draw seeds from the same distribution with fresh random
+// numbers (trial counter 1 + r M + k - 1) and walk until the same chain is
+// found again; K trials give <1/P(chain | n)> = K.  With a cap of M trials the
+// estimate is K = M when no trial matched (flagged).  P(n) = 1 (n is given).
+void orc_inv_prob(void* sp, const int32_t* gi, const double* gd, const orc_params* pp, int N, const double* xD,
+                  const double* nD, const double* xL, const uint8_t* len, const uint8_t* type, const int32_t* obj1,
+                  const int32_t* tgt_prim, const double* tgt_pos, const int8_t* tgt_status, int max_trials,
+                  int repeats, uint64_t seed, double alpha, int32_t* trials, double* inv_prob, int8_t* truncated,
+                  int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  Guide gstore;
+  const Guide* g = make_guide_view(gi, gd, &gstore);
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    trials[c] = 0;
+    inv_prob[c] = 0.0;
+    truncated[c] = 0;
+    if (tgt_status[c] != ST_CONVERGED || repeats < 1 || max_trials < 1) return;
+    int n = len[c];
+    V3d xd = get3d(xD, N, c), xl = get3d(xL, N, c), nd = get3d(nD, N, c);
+    Chain target;
+    target.n = n;
+    target.type = type[c];
+    target.xD = xd;
+    target.xL = xl;
+    for (int i = 0; i < n; ++i) {
+      V3d x(tgt_pos[((size_t)0 * KMAX + i) * N + c], tgt_pos[((size_t)1 * KMAX + i) * N + c],
+            tgt_pos[((size_t)2 * KMAX + i) * N + c]);
+      target.v[i] = make_geo(s, tgt_prim[(size_t)i * N + c], x);
+    }
+    int total = 0;
+    for (int r = 0; r < repeats; ++r) {
+      int K = max_trials;
+      bool found = false;
+      for (int k = 1; k <= max_trials && !found; ++k) {
+        uint64_t trial = 1 + (uint64_t)r * max_trials + (uint64_t)(k - 1);
+        int prim[KMAX];
+        V3d pos[KMAX];
+        if (sample_seed(s, g, p, n, type[c], obj1[c], xd, nd, seed, (uint64_t)c, trial, alpha, prim, pos) != 0)
+          continue;
+        Chain start;
+        if (!load_chain(s, n, type[c], xd, xl, prim, pos, &start)) continue;
+        WalkResult w;
+        walk_core(s, p, start, &w);
+        if (w.status == ST_CONVERGED && chains_match(s, w.chain, target, p.match_rel * p.scale)) {
+          K = k;
+          found = true;
+        }
+      }
+      if (!found) truncated[c] = 1;
+      total += K;
+    }
+    trials[c] = total;
+    inv_prob[c] = (double)total / repeats;
+  });
+}
+
+void orc_fit_guide(int n_samples, const float* samples, int res, int comps, int iters, int min_samples,
+                   const double* lo, const double* hi, double reg, int32_t* valid, double* pi, double* mu,
+                   double* cov, int32_t* count, int nthreads) {
+  EMParams ep;
+  ep.res = res; ep.comps = comps; ep.iters = iters; ep.min_samples = min_samples; ep.reg = reg;
+  for (int a = 0; a < 3; ++a) { ep.lo[a] = lo[a]; ep.hi[a] = hi[a]; }
+  int cells = res * res * res;
+  std::vector<std::vector<int>> members(cells);
+  for (int i = 0; i < n_samples; ++i) {
+    const float* r = samples + 8 * (size_t)i;
+    if (!(r[5] > 0.0f)) continue;
+    int cidx = em_cell_index(ep, r);
+    if (cidx >= 0) members[cidx].push_back(i);
+  }
+  parallel_for(cells, nthreads, [&](int c) {
+    count[c] = (int)members[c].size();
+    em_cell(ep, members[c], samples, &valid[c], pi + (size_t)c * comps, mu + (size_t)c * comps * 2,
+            cov + (size_t)c * comps * 3);
+  });
+}
+
+}  // extern "C"
