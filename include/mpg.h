@@ -1,0 +1,270 @@
+/*
+ * mpg.h -- C ABI of the MI355X batched manifold-walk library (libmpg.so).
+ *
+ * The library implements the data-parallel hot path of manifold path guiding
+ * (Fan et al., "Manifold Path Guiding for Importance Sampling Specular
+ * Chains", ACM TOG 42(6), 2023): seed chains are drawn from a guided
+ * distribution (Sec. 5.4-5.5), driven to admissible specular chains by
+ * manifold walks (Newton's method plus reprojection, Sec. 3), scored with the
+ * sub-path throughput terms kappa and G (Eq. ThroughputEval), and their
+ * reciprocal sampling probability is estimated by repeated independent
+ * trials (Sec. 5.8).  Guide fitting (weighted EM per spatial cell) and an
+ * implicit-function-theorem adjoint of the converged chain complete it.
+ *
+ * Conventions shared by every entry point:
+ *  - Arguments named d_* are device pointers owned by the caller; host
+ *    descriptors are read during the call only.  The library never frees
+ *    caller memory.
+ *  - Per-chain arrays are structure-of-arrays: points [3][N] (component
+ *    major), chain vertices [K][N] and [3][K][N] with K = MPG_KMAX = 8.
+ *  - Every compute call is asynchronous on the given HIP stream (NULL = the
+ *    null stream); it performs no device synchronization and no allocation
+ *    except where stated (scene / guide / workspace creation).
+ *  - Argument errors (NULL where required, N < 0, sizes out of range) are
+ *    detected on the host before any launch and return MPG_ERR_INVALID_ARG;
+ *    HIP launch failures return MPG_ERR_HIP.  mpg_last_error() gives a
+ *    thread-local message for the last non-OK status.
+ *  - Per-chain failures are data, not errors: they are reported in the
+ *    per-chain status array (MPG_CONVERGED ... MPG_BAD_INPUT).
+ */
+#ifndef MPG_H
+#define MPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mpg_status;
+#define MPG_OK 0
+#define MPG_ERR_INVALID_ARG (-1)
+#define MPG_ERR_HIP (-2)
+#define MPG_ERR_OOM (-3)
+#define MPG_ERR_UNSUPPORTED (-4)
+
+/* per-chain status codes */
+#define MPG_CONVERGED 0     /* admissible chain found, sides valid, visible from x_L */
+#define MPG_MAX_ITER 1      /* iteration budget spent without convergence */
+#define MPG_SINGULAR 2      /* a pivot of the block-tridiagonal solve vanished */
+#define MPG_SIDE_INVALID 3  /* converged, but a vertex violates its R / T side condition */
+#define MPG_OCCLUDED 4      /* converged, but x_n cannot see x_L */
+#define MPG_SEED_INVALID 5  /* the seed could not be drawn or deduced */
+#define MPG_FP64_REJECT 6   /* near-singular chain failed the FP64 residual check */
+#define MPG_BAD_INPUT 7     /* non-finite endpoint or chain length outside 1..8 */
+
+#define MPG_MAT_MIRROR 0
+#define MPG_MAT_DIELECTRIC 1
+
+#define MPG_KMAX 8
+#define MPG_PRIM_NONE ((int32_t)0x80000000)
+#define MPG_P0_ANY_OBJECT (-1)
+#define MPG_P0_DIRECTION (-2)
+
+const char* mpg_last_error(void);
+/* version string of the library build */
+const char* mpg_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Scene                                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Sine-sum height field z = z0 + sum_k amp_k sin(freq_k (cos psi_k x + sin psi_k y) + phase_k)
+ * on a res x res vertex grid over [x0,x1] x [y0,y1]; its vertices are
+ * first_vert + j res + i and its triangles first_tri + 2 (j (res-1) + i) + {0,1}.
+ * The amplitudes and phases are the differentiable surface parameters of
+ * manifold_walk_adjoint (two per sine, in declaration order). */
+typedef struct {
+  int32_t obj, res, first_vert, first_tri, n_sines;
+  float x0, x1, y0, y1, z0;
+  float amp[8], freq[8], psi[8], phase[8];
+} mpg_heightfield;
+
+/* Host description of the specular surfaces M_S (Sec. 5.3, operator r).
+ * Triangles carry per-vertex shading normals; analytic spheres use their
+ * exact normal.  Primitive ids: triangles 0..n_tris-1 in this order,
+ * spheres -1 - s.  Each object has a material (MPG_MAT_*) and, for
+ * dielectrics, the index of refraction inside (outside is 1); triangle
+ * windings are counter-clockwise about the outward normal. */
+typedef struct {
+  int32_t n_verts;
+  const float* verts;    /* host [n_verts][3] */
+  const float* normals;  /* host [n_verts][3] */
+  int32_t n_tris;
+  const int32_t* tris;     /* host [n_tris][3] */
+  const int32_t* tri_obj;  /* host [n_tris] */
+  int32_t n_objects;
+  const int32_t* obj_material;  /* host [n_objects] */
+  const float* obj_ior;         /* host [n_objects] */
+  int32_t n_spheres;
+  const float* spheres;       /* host [n_spheres][4]: centre, radius */
+  const int32_t* sphere_obj;  /* host [n_spheres] */
+  float scale;                /* scene scale L (longest side of the specular bounding box) */
+  int32_t n_heightfields;
+  const mpg_heightfield* heightfields;
+} mpg_scene_desc;
+
+typedef struct mpg_scene mpg_scene;
+
+/* Builds the device scene on the current device: uploads geometry, builds a
+ * binned-SAH BVH (64-byte two-child nodes) and per-object area tables.
+ * Allocates device memory; synchronous. */
+mpg_status mpg_scene_create(const mpg_scene_desc* desc, mpg_scene** out);
+void mpg_scene_destroy(mpg_scene* scene);
+/* BVH statistics: node count, maximum depth (the traversal stack needs depth+1 entries). */
+mpg_status mpg_scene_stats(const mpg_scene* scene, int32_t* n_nodes, int32_t* max_depth, int32_t* n_tris);
+
+/* ------------------------------------------------------------------------ */
+/* Batches                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Configurations (x_D, x_L) with their chain length n and type tau (Sec. 3,
+ * Table 1; Eq. eq_div1): bit i of type is 1 for a transmission at vertex
+ * i+1.  obj1 selects the p_0 draw of the first vertex: an object id,
+ * MPG_P0_ANY_OBJECT or MPG_P0_DIRECTION. */
+typedef struct {
+  int32_t N;
+  const float* d_xD;    /* [3][N] shading points */
+  const float* d_nD;    /* [3][N] unit normals at x_D */
+  const float* d_xL;    /* [3][N] point-light positions */
+  const uint8_t* d_len;   /* [N] 1..8 */
+  const uint8_t* d_type;  /* [N] */
+  const int32_t* d_obj1;  /* [N] */
+} mpg_endpoints;
+
+/* Chains: primitive id and position of each specular vertex. */
+typedef struct {
+  int32_t* d_prim; /* [K][N] */
+  float* d_pos;    /* [3][K][N] */
+} mpg_chains;
+
+/* Walk outputs; any pointer may be NULL to skip it. */
+typedef struct {
+  int8_t* d_status;        /* [N] MPG_CONVERGED ... */
+  uint8_t* d_iters;        /* [N] Newton trials used */
+  uint64_t* d_solution_id; /* [N] hash of (n, type, primitive ids); 0 unless converged */
+  float* d_G;              /* [N] generalized geometric term */
+  float* d_kappa;          /* [N] product of Fresnel / mirror coefficients */
+  float* d_residual;       /* [N] max-norm of the constraint at the returned chain */
+} mpg_walk_out;
+
+#define MPG_FORM_PLAIN 0
+#define MPG_FORM_PERSISTENT 1
+
+typedef struct {
+  int32_t max_iter;          /* Newton trials per walk (default 20) */
+  float tol_vertex;          /* converged when a full step moves every vertex <= tol_vertex * scale (1e-4) */
+  float tol_residual;        /* ... and leaves max|C| <= tol_residual (1e-5) */
+  float scale;               /* scene scale L */
+  float tmin_rel;            /* ray offset, relative to L (1e-5) */
+  float match_rel;           /* trial-to-target match distance, relative to L (1e-3) */
+  float fp64_cond_threshold; /* FP64 residual check when the condition estimate exceeds this (1e4) */
+  float fp64_graze_cos;      /* ... or when a vertex scatters with |cos| below this (0.02) */
+  float cone_cos;            /* MPG_P0_DIRECTION: cosine of the cone half-angle about n_D */
+  int32_t form;              /* MPG_FORM_PLAIN or MPG_FORM_PERSISTENT */
+  int32_t bucketing;         /* persistent form: sort chains by length first (1) or not (0) */
+  int32_t waves_per_group;   /* wavefronts per workgroup (1, 2, 4) */
+  int32_t stack_depth;       /* LDS traversal stack entries per lane (>= BVH depth + 1; 0 = automatic) */
+  int32_t refill;            /* persistent form: lanes pull a new chain as soon as theirs finishes (1) */
+  int32_t max_len;           /* longest chain in the batch (1..8, default 8); longer chains get MPG_BAD_INPUT */
+} mpg_walk_params;
+
+/* Fills defaults for a scene of scale L. */
+mpg_status mpg_walk_params_default(float scale, mpg_walk_params* out);
+
+/* Device scratch for the persistent form, estimate_inv_prob's queue and
+ * fit_guide's binning, sized for up to max_chains chains / samples.
+ * Allocates device memory; synchronous. */
+typedef struct mpg_workspace mpg_workspace;
+mpg_status mpg_workspace_create(int32_t max_chains, mpg_workspace** out);
+void mpg_workspace_destroy(mpg_workspace* ws);
+
+/* ------------------------------------------------------------------------ */
+/* Guide: 8-component 2-D Gaussian mixtures over (x, y) of x_1 on a res^3     */
+/* grid of cells over the x_D bounding box.                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct mpg_guide mpg_guide;
+
+typedef struct {
+  float lo[3], hi[3]; /* x_D bounding box of the grid */
+  int32_t res;        /* cells per axis (32) */
+  int32_t comps;      /* mixture components (8) */
+  int32_t em_iters;   /* EM iterations (30) */
+  int32_t min_samples;/* cells with fewer samples stay invalid (p_0 only) (16) */
+  float reg;          /* covariance regularizer added to the diagonal (1e-6 L^2) */
+  int32_t target_obj; /* object the guided (x, y) is lifted onto */
+} mpg_guide_desc;
+
+/* Allocates an empty guide (every cell invalid).  Synchronous. */
+mpg_status mpg_guide_create(const mpg_guide_desc* desc, mpg_guide** out);
+void mpg_guide_destroy(mpg_guide* g);
+/* Host upload / download of the per-cell mixtures.  Layouts: valid [cells],
+ * pi [cells][comps], mu [cells][comps][2], cov [cells][comps][3] (xx, xy, yy),
+ * count [cells] (download only; may be NULL).  Synchronous. */
+mpg_status mpg_guide_upload(mpg_guide* g, const int32_t* valid, const float* pi, const float* mu, const float* cov);
+mpg_status mpg_guide_download(const mpg_guide* g, int32_t* valid, float* pi, float* mu, float* cov,
+                              int32_t* count);
+
+/* ------------------------------------------------------------------------ */
+/* Hot path                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Draws one seed chain per configuration (Sec. 5.4-5.5): with probability
+ * alpha (or always when guide is NULL or the cell is invalid) from p_0,
+ * otherwise from the cell's Gaussian mixture over (x, y) lifted onto the
+ * guide's target object; then w_D = normalize(p - x_D), x_1 = r(x_D, w_D)
+ * and x_2..x_n by Eq. (deduction).  Random numbers: Philox4x64-10 with key
+ * (philox_seed, 0) and counter (chain, trial, attempt, 0).  Writes prim/pos
+ * for vertices 0..n-1 and d_status (0 or MPG_SEED_INVALID / MPG_BAD_INPUT). */
+mpg_status sample_seeds(const mpg_scene* scene, const mpg_guide* guide, const mpg_walk_params* params,
+                        const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, float alpha,
+                        mpg_chains* out, int8_t* d_status, void* hip_stream);
+
+/* Manifold walks (Sec. 3): Newton's method on the generalized half-vector
+ * constraints with a block-tridiagonal Jacobian, reprojection by ray casting,
+ * step halving; then side / visibility checks, an FP64 residual check for
+ * near-singular chains, and G and kappa (Eq. ThroughputEval).  seeds and out
+ * may alias.  d_seed_status (nullable) marks seeds to skip.  The persistent
+ * form needs a workspace of at least N chains. */
+mpg_status manifold_walk_batch(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
+                               const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
+                               const mpg_walk_out* wout, mpg_workspace* ws, void* hip_stream);
+
+/* Reciprocal probability by repeated independent trials (Sec. 5.8): for each
+ * target with status MPG_CONVERGED, seeds are redrawn from the same
+ * distribution (trial counters 1 + r max_trials + k - 1) and walked until one
+ * reaches the target again (same objects, every vertex within match_rel L);
+ * K = that trial count, or max_trials when none matched (d_truncated = 1).
+ * d_inv_prob = mean_r K_r / P(n) with P(n) = 1 (n is given), d_trials =
+ * sum_r K_r.  Other targets get 0.  d_truncated may be NULL. */
+mpg_status estimate_inv_prob(const mpg_scene* scene, const mpg_guide* guide, const mpg_walk_params* params,
+                             const mpg_endpoints* ep, const mpg_chains* target, const int8_t* d_target_status,
+                             int32_t max_trials, int32_t repeats, uint64_t philox_seed, float alpha,
+                             int32_t* d_trials, float* d_inv_prob, uint8_t* d_truncated,
+                             mpg_workspace* ws, void* hip_stream);
+
+/* Weighted EM per cell (weights w = T <1/P>, Eq. eq_weight) on 32-byte sample
+ * records {x_D.x, x_D.y, x_D.z, u, v, w, 0, 0} (u, v = x, y of x_1); samples
+ * with w <= 0 are ignored.  Initialization per cell: the weighted mean and
+ * covariance (+ reg I), component j centred on the cell's sample of rank
+ * floor((j + 1/2) m / comps) in input order, equal weights; then exactly
+ * em_iters iterations.  Needs a workspace of at least n_samples. */
+mpg_status fit_guide(const mpg_scene* scene, const float* d_samples, int32_t n_samples, mpg_guide* guide,
+                     mpg_workspace* ws, void* hip_stream);
+
+/* Adjoint of converged chains by the implicit function theorem (Sec. 5.2):
+ * given cotangents of the vertex positions (d_grad_pos [3][K][N], nullable)
+ * and of G (d_grad_G [N], nullable), accumulates the gradients with respect
+ * to x_D (d_grad_xD [3][N]), x_L (d_grad_xL [3][N]) and the height-field
+ * parameters (d_grad_theta [P], P = 2 * sum of n_sines, added atomically).
+ * Chains whose status is not MPG_CONVERGED contribute nothing. */
+mpg_status manifold_walk_adjoint(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
+                                 const mpg_chains* converged, const int8_t* d_status, const float* d_grad_pos,
+                                 const float* d_grad_G, float* d_grad_xD, float* d_grad_xL, float* d_grad_theta,
+                                 void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPG_H */

@@ -81,7 +81,7 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
-def params(scale: float, max_iter: int = 20, tol_vertex: float = 1e-4, tol_residual: float = 1e-4,
+def params(scale: float, max_iter: int = 20, tol_vertex: float = 1e-4, tol_residual: float = 1e-5,
            tmin_rel: float = 1e-5, match_rel: float = 1e-3, polish_tol: float = 1e-12,
            cone_cos: float = 0.0) -> orc_params:
     return orc_params(max_iter, tol_vertex, tol_residual, scale, tmin_rel, match_rel, polish_tol, cone_cos)

@@ -48,6 +48,7 @@ enum Status : int8_t {
   ST_SEED_INVALID = 5,
   ST_FP64_REJECT = 6,
   ST_BAD_INPUT = 7,
+  ST_STALLED = 8,  // internal: tiny full step that no longer lowers the residual
 };
 enum Material : int { MAT_MIRROR = 0, MAT_DIELECTRIC = 1 };
 
@@ -582,11 +583,15 @@ struct WalkResult {
 // Manifold walk (Sec. 3): Newton's method with reprojection and the
 // step-length rule below (the paper leaves the rule to its citations):
 //   beta = 1; every trial step counts as one iteration;
-//   trial x' = reproject(x + beta delta); a failed reprojection halves beta;
-//   converged when beta == 1, max_i |delta_i| <= tol_vertex L and
+//   the trial length is beta, or 1 when the full step max_i |delta_i| is
+//   within tol_vertex L; trial x' = reproject(x + length delta);
+//   a failed reprojection halves the length;
+//   converged when the full step is within tol_vertex L and
 //   |C(x')|_inf <= tol_residual (x' is kept);
-//   otherwise accept iff |C(x')|_2 < |C(x)|_2 (then beta = min(1, 2 beta)),
-//   else halve beta.
+//   otherwise accept iff |C(x')|_2 < |C(x)|_2 (then beta = min(1, 2 length));
+//   a rejected full step that was within tol_vertex L stops the walk as
+//   stalled (precision floor), handed to the FP64 check;
+//   any other rejection sets beta = length / 2.
 static void walk_core(const Scene& s, const Params& p, const Chain& start, WalkResult* res) {
   const int m = 2 * start.n;
   const double tmin = p.tmin_rel * p.scale;
@@ -599,16 +604,17 @@ static void walk_core(const Scene& s, const Params& p, const Chain& start, WalkR
   for (int it = 1; it <= p.max_iter; ++it) {
     res->iters = it;
     double step = 0.0;
+    for (int i = 0; i < c.n; ++i) step = std::max(step, norm(disp[i]));
+    // once the full Newton step is within the vertex tolerance it is always tried whole
+    bool small = step <= p.tol_vertex * p.scale;
+    double bt = small ? 1.0 : beta;
     V3d target[KMAX];
-    for (int i = 0; i < c.n; ++i) {
-      step = std::max(step, norm(disp[i]));
-      target[i] = c.v[i].x + disp[i] * beta;
-    }
+    for (int i = 0; i < c.n; ++i) target[i] = c.v[i].x + disp[i] * bt;
     Chain trial;
-    if (!reproject(s, c, target, tmin, &trial)) { beta *= 0.5; continue; }
+    if (!reproject(s, c, target, tmin, &trial)) { beta = 0.5 * bt; continue; }
     double Ct[2 * KMAX];
     residual(trial, Ct);
-    if (beta == 1.0 && step <= p.tol_vertex * p.scale && inf_norm(Ct, m) <= p.tol_residual) {
+    if (small && inf_norm(Ct, m) <= p.tol_residual) {
       c = trial;
       res->status = ST_CONVERGED;
       break;
@@ -616,9 +622,14 @@ static void walk_core(const Scene& s, const Params& p, const Chain& start, WalkR
     if (two_norm(Ct, m) < two_norm(C, m)) {
       c = trial;
       if (!newton_direction(c, C, disp)) { res->status = ST_SINGULAR; break; }
-      beta = std::min(1.0, 2.0 * beta);
+      beta = std::min(1.0, 2.0 * bt);
+    } else if (small) {
+      // the full step is within tolerance but no longer lowers the residual:
+      // the walk has reached its precision floor; the FP64 check decides
+      res->status = ST_STALLED;
+      break;
     } else {
-      beta *= 0.5;
+      beta = 0.5 * bt;
     }
   }
   res->chain = c;
@@ -671,7 +682,9 @@ static double chain_kappa(const Chain& c) {
     V3d xp = i == 0 ? c.xD : c.v[i - 1].x;
     V3d wi = normalize(xp - g.x);
     V3d ns = geo_shading<double>(g, g.x);
-    double F = fresnel_dielectric(dot(wi, ns), c.ea[i], c.T(i) ? c.eb[i] : c.ea[i]);
+    // physical indices: incident side of w_i, transmitted side the other
+    bool outside = dot(wi, g.ng) > 0.0;
+    double F = fresnel_dielectric(dot(wi, ns), outside ? 1.0 : g.ior, outside ? g.ior : 1.0);
     k *= c.T(i) ? (1.0 - F) : F;
   }
   return k;
@@ -719,7 +732,7 @@ static bool visible_to_light(const Scene& s, const Params& p, const Chain& c) {
   V3d d = c.xL - last.x;
   double dist = norm(d);
   Hit h = cast_ray(s, last.x, d * (1.0 / dist), last.prim, p.tmin_rel * p.scale);
-  return !(h.ok && h.t < dist * (1.0 - 1e-9));
+  return !(h.ok && h.t < dist * (1.0 - 1e-6));
 }
 
 static bool load_chain(const Scene& s, int n, int type, const V3d& xD, const V3d& xL, const int* prim,
@@ -748,12 +761,18 @@ static void walk_chain(const Scene& s, const Params& p, int n, int type, const V
   if (!finite3(xD) || !finite3(xL) || n < 1 || n > KMAX) { res->status = ST_BAD_INPUT; return; }
   if (!load_chain(s, n, type, xD, xL, prim, pos, &c)) { res->status = ST_SEED_INVALID; res->chain = c; return; }
   walk_core(s, p, c, res);
-  if (res->status != ST_CONVERGED) return;
-  if (do_polish) polish(s, p, res);
+  bool stalled = res->status == ST_STALLED;
+  if (res->status != ST_CONVERGED && !stalled) return;
+  if (do_polish || stalled) polish(s, p, res);
   else {
     double C[2 * KMAX];
     residual(res->chain, C);
     res->residual = inf_norm(C, 2 * n);
+  }
+  // FP64 check of a stalled walk: accepted when the FP64 residual is < 1e-6
+  if (stalled) {
+    if (!(res->residual < 1e-6)) { res->status = ST_FP64_REJECT; return; }
+    res->status = ST_CONVERGED;
   }
   if (!side_ok(res->chain)) { res->status = ST_SIDE_INVALID; return; }
   if (!visible_to_light(s, p, res->chain)) { res->status = ST_OCCLUDED; return; }
@@ -799,8 +818,9 @@ static bool sample_p0_point(const Scene& s, const Params& p, int obj1, const V3d
   if (obj1 == -2) {
     V3d ax = normalize(nD), b1, b2;
     onb(ax, &b1, &b2);
-    double ct = 1.0 - u2 * (1.0 - p.cone_cos);
-    double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+    double v = u2 * (1.0 - p.cone_cos);  // 1 - cos(theta)
+    double ct = 1.0 - v;
+    double st = std::sqrt(std::max(0.0, v * (2.0 - v)));
     double ph = 2.0 * kPi * u3;
     *pt = xD + b1 * (st * std::cos(ph)) + b2 * (st * std::sin(ph)) + ax * ct;
     return true;
@@ -829,8 +849,9 @@ static bool sample_p0_point(const Scene& s, const Params& p, int obj1, const V3d
   V3d ax = oc * (1.0 / d), b1, b2;
   onb(ax, &b1, &b2);
   double cmax = s.sr[k] / d;
-  double ct = 1.0 - u2 * (1.0 - cmax);
-  double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  double v = u2 * (1.0 - cmax);  // 1 - cos(theta)
+  double ct = 1.0 - v;
+  double st = std::sqrt(std::max(0.0, v * (2.0 - v)));
   double ph = 2.0 * kPi * u3;
   *pt = s.sc[k] + (b1 * (st * std::cos(ph)) + b2 * (st * std::sin(ph)) + ax * ct) * s.sr[k];
   return true;
@@ -1329,7 +1350,8 @@ void orc_inv_prob(void* sp, const int32_t* gi, const double* gd, const orc_param
         if (!load_chain(s, n, type[c], xd, xl, prim, pos, &start)) continue;
         WalkResult w;
         walk_core(s, p, start, &w);
-        if (w.status == ST_CONVERGED && chains_match(s, w.chain, target, p.match_rel * p.scale)) {
+        bool conv = w.status == ST_CONVERGED || w.status == ST_STALLED;
+        if (conv && chains_match(s, w.chain, target, p.match_rel * p.scale)) {
           K = k;
           found = true;
         }

@@ -1,0 +1,344 @@
+"""Python binding of libmpg (MI355X batched manifold walks).
+
+Thin ctypes marshalling over the C ABI in ``include/mpg.h``: every step of the
+path runs in the HIP library; PyTorch provides device memory and the stream.
+The binding refuses to run without the built library (no CPU fallback).
+
+Names follow the C ABI: :func:`sample_seeds`, :func:`manifold_walk_batch`,
+:func:`estimate_inv_prob`, :func:`fit_guide`, :func:`manifold_walk_adjoint`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpg.so")
+KMAX = 8
+PRIM_NONE = -2 ** 31
+
+CONVERGED, MAX_ITER, SINGULAR, SIDE_INVALID, OCCLUDED, SEED_INVALID, FP64_REJECT, BAD_INPUT = range(8)
+STATUS_NAMES = ["converged", "max_iter", "singular", "side_invalid", "occluded", "seed_invalid", "fp64_reject",
+                "bad_input"]
+FORM_PLAIN, FORM_PERSISTENT = 0, 1
+P0_ANY_OBJECT, P0_DIRECTION = -1, -2
+
+_lib = None
+
+
+class MPGError(RuntimeError):
+    pass
+
+
+P = C.c_void_p
+I32 = C.c_int32
+F32 = C.c_float
+
+
+class mpg_heightfield(C.Structure):
+    _fields_ = [("obj", I32), ("res", I32), ("first_vert", I32), ("first_tri", I32), ("n_sines", I32),
+                ("x0", F32), ("x1", F32), ("y0", F32), ("y1", F32), ("z0", F32),
+                ("amp", F32 * 8), ("freq", F32 * 8), ("psi", F32 * 8), ("phase", F32 * 8)]
+
+
+class mpg_scene_desc(C.Structure):
+    _fields_ = [("n_verts", I32), ("verts", P), ("normals", P), ("n_tris", I32), ("tris", P), ("tri_obj", P),
+                ("n_objects", I32), ("obj_material", P), ("obj_ior", P), ("n_spheres", I32), ("spheres", P),
+                ("sphere_obj", P), ("scale", F32), ("n_heightfields", I32), ("heightfields", P)]
+
+
+class mpg_endpoints(C.Structure):
+    _fields_ = [("N", I32), ("d_xD", P), ("d_nD", P), ("d_xL", P), ("d_len", P), ("d_type", P), ("d_obj1", P)]
+
+
+class mpg_chains(C.Structure):
+    _fields_ = [("d_prim", P), ("d_pos", P)]
+
+
+class mpg_walk_out(C.Structure):
+    _fields_ = [("d_status", P), ("d_iters", P), ("d_solution_id", P), ("d_G", P), ("d_kappa", P),
+                ("d_residual", P)]
+
+
+class mpg_walk_params(C.Structure):
+    _fields_ = [("max_iter", I32), ("tol_vertex", F32), ("tol_residual", F32), ("scale", F32), ("tmin_rel", F32),
+                ("match_rel", F32), ("fp64_cond_threshold", F32), ("fp64_graze_cos", F32), ("cone_cos", F32), ("form", I32),
+                ("bucketing", I32), ("waves_per_group", I32), ("stack_depth", I32), ("refill", I32),
+                ("max_len", I32)]
+
+
+class mpg_guide_desc(C.Structure):
+    _fields_ = [("lo", F32 * 3), ("hi", F32 * 3), ("res", I32), ("comps", I32), ("em_iters", I32),
+                ("min_samples", I32), ("reg", F32), ("target_obj", I32)]
+
+
+def lib():
+    """Load libmpg.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MPGError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        L.mpg_last_error.restype = C.c_char_p
+        L.mpg_version.restype = C.c_char_p
+        L.mpg_scene_create.argtypes = [C.POINTER(mpg_scene_desc), C.POINTER(P)]
+        L.mpg_scene_destroy.argtypes = [P]
+        L.mpg_scene_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
+        L.mpg_walk_params_default.argtypes = [F32, C.POINTER(mpg_walk_params)]
+        L.mpg_workspace_create.argtypes = [I32, C.POINTER(P)]
+        L.mpg_workspace_destroy.argtypes = [P]
+        L.mpg_guide_create.argtypes = [C.POINTER(mpg_guide_desc), C.POINTER(P)]
+        L.mpg_guide_destroy.argtypes = [P]
+        L.mpg_guide_upload.argtypes = [P, P, P, P, P]
+        L.mpg_guide_download.argtypes = [P, P, P, P, P, P]
+        L.sample_seeds.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.c_uint64,
+                                   C.c_uint32, F32, C.POINTER(mpg_chains), P, P]
+        L.manifold_walk_batch.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                          C.POINTER(mpg_chains), P, C.POINTER(mpg_chains), C.POINTER(mpg_walk_out),
+                                          P, P]
+        L.estimate_inv_prob.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                        C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, F32, P, P, P, P, P]
+        L.fit_guide.argtypes = [P, P, I32, P, P, P]
+        L.manifold_walk_adjoint.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                            C.POINTER(mpg_chains), P, P, P, P, P, P, P]
+        for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
+                     "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
+                     "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint"]:
+            getattr(L, name).restype = I32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise MPGError(f"{what} failed ({rc}): {lib().mpg_last_error().decode()}")
+
+
+def version() -> str:
+    return lib().mpg_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(a, dtype=None, device="cuda"):
+    torch = _torch()
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device).contiguous()
+
+
+# ---------------------------------------------------------------------------
+# handles
+# ---------------------------------------------------------------------------
+
+class Scene:
+    """Device scene built from a ``workloads.Scene`` (host arrays)."""
+
+    def __init__(self, sc):
+        L = lib()
+        self._keep = [np.ascontiguousarray(sc.verts, np.float32), np.ascontiguousarray(sc.normals, np.float32),
+                      np.ascontiguousarray(sc.tris, np.int32), np.ascontiguousarray(sc.tri_obj, np.int32),
+                      np.ascontiguousarray(sc.obj_material, np.int32), np.ascontiguousarray(sc.obj_ior, np.float32),
+                      np.ascontiguousarray(sc.spheres, np.float32).reshape(-1),
+                      np.ascontiguousarray(sc.sphere_obj, np.int32)]
+        hfs = (mpg_heightfield * max(1, len(sc.heightfields)))()
+        for k, hf in enumerate(sc.heightfields):
+            h = hfs[k]
+            h.obj, h.res, h.first_vert, h.first_tri, h.n_sines = hf.obj, hf.res, hf.first_vert, hf.first_tri, len(hf.amp)
+            h.x0, h.x1, h.y0, h.y1, h.z0 = hf.x0, hf.x1, hf.y0, hf.y1, hf.z0
+            for j in range(len(hf.amp)):
+                h.amp[j], h.freq[j], h.psi[j], h.phase[j] = hf.amp[j], hf.freq[j], hf.psi[j], hf.phase[j]
+        self._hfs = hfs
+        v, n, t, to, m, io, s, so = self._keep
+        d = mpg_scene_desc(v.shape[0], v.ctypes.data, n.ctypes.data, t.shape[0], t.ctypes.data, to.ctypes.data,
+                           m.shape[0], m.ctypes.data, io.ctypes.data, so.shape[0], s.ctypes.data, so.ctypes.data,
+                           float(sc.scale), len(sc.heightfields), C.cast(hfs, C.c_void_p))
+        h = P()
+        _check(L.mpg_scene_create(C.byref(d), C.byref(h)), "mpg_scene_create")
+        self.h = h
+        self.scale = float(sc.scale)
+        self.n_params = 2 * sum(len(hf.amp) for hf in sc.heightfields)
+        self.src = sc
+
+    def stats(self):
+        a, b, c = I32(), I32(), I32()
+        _check(lib().mpg_scene_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "mpg_scene_stats")
+        return dict(n_nodes=a.value, max_depth=b.value, n_tris=c.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mpg_scene_destroy(self.h)
+            self.h = None
+
+
+class Workspace:
+    def __init__(self, max_chains: int):
+        h = P()
+        _check(lib().mpg_workspace_create(int(max_chains), C.byref(h)), "mpg_workspace_create")
+        self.h = h
+        self.cap = int(max_chains)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mpg_workspace_destroy(self.h)
+            self.h = None
+
+
+class Guide:
+    def __init__(self, lo, hi, res=32, comps=8, em_iters=30, min_samples=16, reg=None, scale=4.0, target_obj=0):
+        reg = 1e-6 * scale * scale if reg is None else reg
+        self.desc = mpg_guide_desc((F32 * 3)(*lo), (F32 * 3)(*hi), res, comps, em_iters, min_samples, reg,
+                                   target_obj)
+        h = P()
+        _check(lib().mpg_guide_create(C.byref(self.desc), C.byref(h)), "mpg_guide_create")
+        self.h = h
+        self.res, self.comps, self.cells = res, comps, res ** 3
+
+    def upload(self, valid, pi, mu, cov):
+        a = [np.ascontiguousarray(valid, np.int32), np.ascontiguousarray(pi, np.float32),
+             np.ascontiguousarray(mu, np.float32), np.ascontiguousarray(cov, np.float32)]
+        _check(lib().mpg_guide_upload(self.h, *[x.ctypes.data for x in a]), "mpg_guide_upload")
+
+    def download(self):
+        C_, K = self.cells, self.comps
+        valid = np.zeros(C_, np.int32)
+        pi = np.zeros((C_, K), np.float32)
+        mu = np.zeros((C_, K, 2), np.float32)
+        cov = np.zeros((C_, K, 3), np.float32)
+        count = np.zeros(C_, np.int32)
+        _check(lib().mpg_guide_download(self.h, valid.ctypes.data, pi.ctypes.data, mu.ctypes.data, cov.ctypes.data,
+                                        count.ctypes.data), "mpg_guide_download")
+        return dict(valid=valid, pi=pi, mu=mu, cov=cov, count=count)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mpg_guide_destroy(self.h)
+            self.h = None
+
+
+def walk_params(scale: float, **kw) -> mpg_walk_params:
+    p = mpg_walk_params()
+    _check(lib().mpg_walk_params_default(float(scale), C.byref(p)), "mpg_walk_params_default")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Endpoints:
+    """Device copy of a ``workloads.Endpoints`` batch."""
+
+    def __init__(self, ep, device="cuda"):
+        torch = _torch()
+        self.N = ep.n
+        self.xD = _dev(ep.xD, torch.float32, device)
+        self.nD = _dev(ep.nD, torch.float32, device)
+        self.xL = _dev(ep.xL, torch.float32, device)
+        self.len = _dev(ep.length, torch.uint8, device)
+        self.type = _dev(ep.types, torch.uint8, device)
+        self.obj1 = _dev(ep.obj1, torch.int32, device)
+
+    def c(self) -> mpg_endpoints:
+        return mpg_endpoints(self.N, self.xD.data_ptr(), self.nD.data_ptr(), self.xL.data_ptr(),
+                             self.len.data_ptr(), self.type.data_ptr(), self.obj1.data_ptr())
+
+
+def empty_chains(N, device="cuda"):
+    torch = _torch()
+    return (torch.full((KMAX, N), PRIM_NONE, dtype=torch.int32, device=device),
+            torch.zeros((3, KMAX, N), dtype=torch.float32, device=device))
+
+
+# ---------------------------------------------------------------------------
+# hot path
+# ---------------------------------------------------------------------------
+
+def sample_seeds(scene: Scene, ep: Endpoints, params: mpg_walk_params, seed=0, trial=0, alpha=0.5,
+                 guide: Optional[Guide] = None, out=None):
+    torch = _torch()
+    prim, pos = out if out is not None else empty_chains(ep.N, ep.xD.device)
+    st = torch.zeros(ep.N, dtype=torch.int8, device=ep.xD.device)
+    ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
+    _check(lib().sample_seeds(scene.h, guide.h if guide else None, C.byref(params), C.byref(ep.c()), int(seed),
+                              int(trial), float(alpha), C.byref(ch), st.data_ptr(), _stream()), "sample_seeds")
+    return prim, pos, st
+
+
+def walk_outputs(N, device="cuda"):
+    torch = _torch()
+    return dict(status=torch.zeros(N, dtype=torch.int8, device=device),
+                iters=torch.zeros(N, dtype=torch.uint8, device=device),
+                sol=torch.zeros(N, dtype=torch.int64, device=device),
+                G=torch.zeros(N, dtype=torch.float32, device=device),
+                kappa=torch.zeros(N, dtype=torch.float32, device=device),
+                residual=torch.zeros(N, dtype=torch.float32, device=device))
+
+
+def manifold_walk_batch(scene: Scene, params: mpg_walk_params, ep: Endpoints, seed_prim, seed_pos,
+                        seed_status=None, out_prim=None, out_pos=None, outs=None, ws: Optional[Workspace] = None):
+    """Walks every chain.  Returns (prim, pos, outputs dict).  out_* may alias the seeds."""
+    if out_prim is None:
+        out_prim, out_pos = empty_chains(ep.N, ep.xD.device)
+    outs = outs if outs is not None else walk_outputs(ep.N, ep.xD.device)
+    seeds = mpg_chains(seed_prim.data_ptr(), seed_pos.data_ptr())
+    oc = mpg_chains(out_prim.data_ptr(), out_pos.data_ptr())
+    wo = mpg_walk_out(outs["status"].data_ptr(), outs["iters"].data_ptr(), outs["sol"].data_ptr(),
+                      outs["G"].data_ptr(), outs["kappa"].data_ptr(), outs["residual"].data_ptr())
+    _check(lib().manifold_walk_batch(scene.h, C.byref(params), C.byref(ep.c()), C.byref(seeds), _ptr(seed_status),
+                                     C.byref(oc), C.byref(wo), ws.h if ws else None, _stream()),
+           "manifold_walk_batch")
+    return out_prim, out_pos, outs
+
+
+def estimate_inv_prob(scene: Scene, params: mpg_walk_params, ep: Endpoints, tprim, tpos, tstatus, max_trials=64,
+                      repeats=1, seed=0, alpha=0.5, guide: Optional[Guide] = None, ws: Optional[Workspace] = None,
+                      outs=None):
+    torch = _torch()
+    dev = ep.xD.device
+    if outs is None:
+        outs = (torch.zeros(ep.N, dtype=torch.int32, device=dev), torch.zeros(ep.N, dtype=torch.float32, device=dev),
+                torch.zeros(ep.N, dtype=torch.uint8, device=dev))
+    trials, inv, trunc = outs
+    tc = mpg_chains(tprim.data_ptr(), tpos.data_ptr())
+    _check(lib().estimate_inv_prob(scene.h, guide.h if guide else None, C.byref(params), C.byref(ep.c()),
+                                   C.byref(tc), tstatus.data_ptr(), int(max_trials), int(repeats), int(seed),
+                                   float(alpha), trials.data_ptr(), inv.data_ptr(), trunc.data_ptr(),
+                                   ws.h if ws else None, _stream()), "estimate_inv_prob")
+    return trials, inv, trunc
+
+
+def fit_guide(scene: Scene, samples, guide: Guide, ws: Workspace):
+    """samples: float32 device tensor [M, 8] (x_D, u, v, w, 0, 0)."""
+    _check(lib().fit_guide(scene.h, samples.data_ptr(), int(samples.shape[0]), guide.h, ws.h, _stream()),
+           "fit_guide")
+    return guide
+
+
+def manifold_walk_adjoint(scene: Scene, params: mpg_walk_params, ep: Endpoints, prim, pos, status, grad_pos=None,
+                          grad_G=None, grad_xD=None, grad_xL=None, grad_theta=None):
+    torch = _torch()
+    dev = ep.xD.device
+    grad_xD = torch.zeros((3, ep.N), dtype=torch.float32, device=dev) if grad_xD is None else grad_xD
+    grad_xL = torch.zeros((3, ep.N), dtype=torch.float32, device=dev) if grad_xL is None else grad_xL
+    if grad_theta is None:
+        grad_theta = torch.zeros(max(1, scene.n_params), dtype=torch.float32, device=dev)
+    ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
+    _check(lib().manifold_walk_adjoint(scene.h, C.byref(params), C.byref(ep.c()), C.byref(ch), status.data_ptr(),
+                                       _ptr(grad_pos), _ptr(grad_G), grad_xD.data_ptr(), grad_xL.data_ptr(),
+                                       grad_theta.data_ptr(), _stream()), "manifold_walk_adjoint")
+    return grad_xD, grad_xL, grad_theta

@@ -1,0 +1,772 @@
+// libmpg: kernels and the C ABI declared in include/mpg.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpg.h"
+#include "mpg_device.h"
+#include "mpg_scene.h"
+
+using namespace mpg;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+static mpg_status fail(mpg_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(MPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* mpg_last_error(void) { return g_err.c_str(); }
+extern "C" const char* mpg_version(void) { return "mpg 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct mpg_scene {
+  DevScene dev;
+  std::vector<void*> allocs;
+  int n_nodes = 0, max_depth = 0, n_tris = 0, n_verts = 0;
+  std::vector<mpg_heightfield> hfs;
+  float scale = 1.0f;
+  int device = 0;
+};
+
+struct mpg_workspace {
+  int32_t cap = 0;
+  int32_t* perm = nullptr;     // [cap] chain order for the persistent form
+  int32_t* counters = nullptr; // [64] histogram / offsets / queue heads
+  int32_t* aux = nullptr;      // [cap] scratch (sample cell ids, sorted indices)
+  std::vector<void*> allocs;
+};
+
+struct mpg_guide {
+  mpg_guide_desc desc;
+  int cells = 0;
+  int32_t* valid = nullptr;
+  float* pi = nullptr;
+  float* mu = nullptr;
+  float* cov = nullptr;
+  float* chol = nullptr;
+  int32_t* count = nullptr;
+  std::vector<void*> allocs;
+  DevGuide dev() const {
+    DevGuide g;
+    g.valid = valid; g.pi = pi; g.mu = mu; g.chol = chol;
+    for (int a = 0; a < 3; ++a) { g.lo[a] = desc.lo[a]; g.hi[a] = desc.hi[a]; }
+    g.res = desc.res; g.comps = desc.comps; g.target_obj = desc.target_obj;
+    return g;
+  }
+};
+
+template <class T>
+static hipError_t dalloc(std::vector<void*>& list, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) { list.push_back(q); *p = (T*)q; }
+  return e;
+}
+template <class T>
+static hipError_t upload(std::vector<void*>& list, const T** p, const T* host, size_t count) {
+  T* q = nullptr;
+  hipError_t e = dalloc(list, &q, count);
+  if (e != hipSuccess) return e;
+  if (count) e = hipMemcpy(q, host, count * sizeof(T), hipMemcpyHostToDevice);
+  *p = q;
+  return e;
+}
+static void free_all(std::vector<void*>& list) {
+  for (void* p : list) (void)hipFree(p);
+  list.clear();
+}
+
+// ---------------------------------------------------------------------------
+// scene
+// ---------------------------------------------------------------------------
+extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out) {
+  if (!d || !out) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: NULL argument");
+  if (d->n_tris < 0 || d->n_verts < 0 || d->n_objects <= 0 || d->n_spheres < 0)
+    return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: negative size or no objects");
+  if (d->n_tris > 0 && (!d->verts || !d->normals || !d->tris || !d->tri_obj))
+    return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: missing triangle arrays");
+  if (d->n_tris >= (1 << 24)) return fail(MPG_ERR_UNSUPPORTED, "mpg_scene_create: more than 2^24 triangles");
+  if (d->n_spheres > 0 && (!d->spheres || !d->sphere_obj))
+    return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: missing sphere arrays");
+  if (!d->obj_material || !d->obj_ior) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: missing object arrays");
+  if (d->n_heightfields < 0 || (d->n_heightfields > 0 && !d->heightfields))
+    return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: bad height-field list");
+  for (int t = 0; t < d->n_tris; ++t) {
+    for (int k = 0; k < 3; ++k)
+      if (d->tris[3 * t + k] < 0 || d->tris[3 * t + k] >= d->n_verts)
+        return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: triangle vertex index out of range");
+    if (d->tri_obj[t] < 0 || d->tri_obj[t] >= d->n_objects)
+      return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: triangle object id out of range");
+  }
+  for (int s = 0; s < d->n_spheres; ++s)
+    if (d->sphere_obj[s] < 0 || d->sphere_obj[s] >= d->n_objects || !(d->spheres[4 * s + 3] > 0.0f))
+      return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: bad sphere");
+  for (int o = 0; o < d->n_objects; ++o)
+    if (d->obj_material[o] != MPG_MAT_MIRROR && d->obj_material[o] != MPG_MAT_DIELECTRIC)
+      return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: unknown material");
+
+  mpg_scene* s = new mpg_scene();
+  (void)hipGetDevice(&s->device);
+  s->scale = d->scale;
+  s->n_tris = d->n_tris;
+  s->n_verts = d->n_verts;
+  for (int i = 0; i < d->n_heightfields; ++i) s->hfs.push_back(d->heightfields[i]);
+  auto bail = [&](hipError_t e, const char* what) {
+    free_all(s->allocs);
+    delete s;
+    return fail(MPG_ERR_HIP, std::string("mpg_scene_create: ") + what + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  DevScene& D = s->dev;
+  std::memset(&D, 0, sizeof(D));
+  D.n_tris = d->n_tris;
+  D.n_spheres = d->n_spheres;
+  D.n_objects = d->n_objects;
+  // geometry
+  std::vector<float4> vp(d->n_verts), vn(d->n_verts);
+  float zmax = -INFINITY;
+  for (int i = 0; i < d->n_verts; ++i) {
+    vp[i] = make_float4(d->verts[3 * i], d->verts[3 * i + 1], d->verts[3 * i + 2], 0.f);
+    float nx = d->normals[3 * i], ny = d->normals[3 * i + 1], nz = d->normals[3 * i + 2];
+    float l = std::sqrt(nx * nx + ny * ny + nz * nz);
+    vn[i] = make_float4(nx / l, ny / l, nz / l, 0.f);
+  }
+  std::vector<int4> ti(d->n_tris);
+  for (int t = 0; t < d->n_tris; ++t) {
+    ti[t] = make_int4(d->tris[3 * t], d->tris[3 * t + 1], d->tris[3 * t + 2], d->tri_obj[t]);
+    for (int k = 0; k < 3; ++k) zmax = std::max(zmax, d->verts[3 * d->tris[3 * t + k] + 2]);
+  }
+  std::vector<float> nodes;
+  std::vector<int32_t> order;
+  int depth = 0;
+  int n_nodes = 0;
+  if (d->n_tris > 0) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < 3 * d->n_verts; ++i) { lo = std::min(lo, d->verts[i]); hi = std::max(hi, d->verts[i]); }
+    float pad = 1e-6f * std::max(1.0f, std::max(std::fabs(lo), std::fabs(hi)));
+    n_nodes = mpg_host::build_bvh(d->verts, d->tris, d->n_tris, pad, nodes, order, &depth);
+  }
+  s->n_nodes = n_nodes;
+  s->max_depth = depth;
+  D.n_nodes = n_nodes;
+  std::vector<float4> tv(3 * (size_t)d->n_tris);
+  for (int k = 0; k < d->n_tris; ++k) {
+    int t = order[k];
+    for (int v = 0; v < 3; ++v) {
+      const float* p = d->verts + 3 * (size_t)d->tris[3 * t + v];
+      float w = 0.f;
+      if (v == 0) std::memcpy(&w, &t, 4);
+      tv[3 * (size_t)k + v] = make_float4(p[0], p[1], p[2], w);
+    }
+  }
+  std::vector<int2> oi(d->n_objects);
+  for (int o = 0; o < d->n_objects; ++o) {
+    int ib;
+    float ior = d->obj_ior[o];
+    std::memcpy(&ib, &ior, 4);
+    oi[o] = make_int2(d->obj_material[o], ib);
+  }
+  std::vector<float4> sph(d->n_spheres);
+  for (int k = 0; k < d->n_spheres; ++k) {
+    sph[k] = make_float4(d->spheres[4 * k], d->spheres[4 * k + 1], d->spheres[4 * k + 2], d->spheres[4 * k + 3]);
+    zmax = std::max(zmax, d->spheres[4 * k + 2] + d->spheres[4 * k + 3]);
+  }
+  // area prefix sums (double, input order) per object and over all objects
+  int O = d->n_objects;
+  std::vector<std::vector<double>> cd(O + 1);
+  std::vector<std::vector<int>> cp(O + 1);
+  std::vector<float4> ob(O, make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY));
+  auto add = [&](int key, int prim, double area) {
+    double prev = cd[key].empty() ? 0.0 : cd[key].back();
+    cd[key].push_back(prev + area);
+    cp[key].push_back(prim);
+  };
+  for (int t = 0; t < d->n_tris; ++t) {
+    double P[3][3];
+    for (int v = 0; v < 3; ++v)
+      for (int a = 0; a < 3; ++a) P[v][a] = d->verts[3 * (size_t)d->tris[3 * t + v] + a];
+    double e1[3], e2[3];
+    for (int a = 0; a < 3; ++a) { e1[a] = P[1][a] - P[0][a]; e2[a] = P[2][a] - P[0][a]; }
+    double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    int o = d->tri_obj[t];
+    add(o, t, area);
+    add(O, t, area);
+    for (int v = 0; v < 3; ++v) {
+      ob[o].x = std::min(ob[o].x, (float)P[v][0]); ob[o].y = std::min(ob[o].y, (float)P[v][1]);
+      ob[o].z = std::max(ob[o].z, (float)P[v][0]); ob[o].w = std::max(ob[o].w, (float)P[v][1]);
+    }
+  }
+  for (int k = 0; k < d->n_spheres; ++k) {
+    double r = d->spheres[4 * k + 3];
+    double area = 4.0 * M_PI * r * r;
+    int o = d->sphere_obj[k];
+    add(o, -1 - k, area);
+    add(O, -1 - k, area);
+    ob[o].x = std::min(ob[o].x, sph[k].x - sph[k].w); ob[o].y = std::min(ob[o].y, sph[k].y - sph[k].w);
+    ob[o].z = std::max(ob[o].z, sph[k].x + sph[k].w); ob[o].w = std::max(ob[o].w, sph[k].y + sph[k].w);
+  }
+  std::vector<double> cdf;
+  std::vector<int> cprim;
+  std::vector<int2> crange(O + 1);
+  for (int k = 0; k <= O; ++k) {
+    crange[k] = make_int2((int)cdf.size(), (int)cd[k].size());
+    cdf.insert(cdf.end(), cd[k].begin(), cd[k].end());
+    cprim.insert(cprim.end(), cp[k].begin(), cp[k].end());
+  }
+  D.zmax = zmax;
+  if ((e = upload(s->allocs, &D.nodes, (const float4*)nodes.data(), nodes.size() / 4)) != hipSuccess) return bail(e, "nodes");
+  if ((e = upload(s->allocs, &D.tri_v, tv.data(), tv.size())) != hipSuccess) return bail(e, "triangles");
+  if ((e = upload(s->allocs, &D.tri_idx, ti.data(), ti.size())) != hipSuccess) return bail(e, "triangle ids");
+  if ((e = upload(s->allocs, &D.vpos, vp.data(), vp.size())) != hipSuccess) return bail(e, "positions");
+  if ((e = upload(s->allocs, &D.vnrm, vn.data(), vn.size())) != hipSuccess) return bail(e, "normals");
+  if ((e = upload(s->allocs, &D.obj_info, oi.data(), oi.size())) != hipSuccess) return bail(e, "objects");
+  if ((e = upload(s->allocs, &D.spheres, sph.data(), sph.size())) != hipSuccess) return bail(e, "spheres");
+  std::vector<int> so(d->sphere_obj, d->sphere_obj + d->n_spheres);
+  if ((e = upload(s->allocs, &D.sphere_obj, so.data(), so.size())) != hipSuccess) return bail(e, "sphere objects");
+  if ((e = upload(s->allocs, &D.cdf, cdf.data(), cdf.size())) != hipSuccess) return bail(e, "cdf");
+  if ((e = upload(s->allocs, &D.cdf_prim, cprim.data(), cprim.size())) != hipSuccess) return bail(e, "cdf prims");
+  if ((e = upload(s->allocs, &D.cdf_range, crange.data(), crange.size())) != hipSuccess) return bail(e, "cdf ranges");
+  if ((e = upload(s->allocs, &D.obj_bounds, ob.data(), ob.size())) != hipSuccess) return bail(e, "bounds");
+  *out = s;
+  return MPG_OK;
+}
+
+extern "C" void mpg_scene_destroy(mpg_scene* s) {
+  if (!s) return;
+  free_all(s->allocs);
+  delete s;
+}
+
+extern "C" mpg_status mpg_scene_stats(const mpg_scene* s, int32_t* n_nodes, int32_t* max_depth, int32_t* n_tris) {
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_stats: NULL scene");
+  if (n_nodes) *n_nodes = s->n_nodes;
+  if (max_depth) *max_depth = s->max_depth;
+  if (n_tris) *n_tris = s->n_tris;
+  return MPG_OK;
+}
+
+extern "C" mpg_status mpg_walk_params_default(float scale, mpg_walk_params* p) {
+  if (!p || !(scale > 0.0f)) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_params_default: bad argument");
+  p->max_iter = 20;
+  p->tol_vertex = 1e-4f;
+  p->tol_residual = 1e-5f;
+  p->scale = scale;
+  p->tmin_rel = 1e-5f;
+  p->match_rel = 1e-3f;
+  p->fp64_cond_threshold = 1e4f;
+  p->fp64_graze_cos = 0.02f;
+  p->cone_cos = 0.0f;
+  p->form = MPG_FORM_PLAIN;
+  p->bucketing = 1;
+  p->waves_per_group = 4;
+  p->stack_depth = 0;
+  p->refill = 1;
+  p->max_len = KMAX;
+  return MPG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+extern "C" mpg_status mpg_workspace_create(int32_t max_chains, mpg_workspace** out) {
+  if (!out || max_chains < 0) return fail(MPG_ERR_INVALID_ARG, "mpg_workspace_create: bad argument");
+  mpg_workspace* w = new mpg_workspace();
+  w->cap = max_chains;
+  hipError_t e;
+  if ((e = dalloc(w->allocs, &w->perm, (size_t)max_chains + 8 * 64)) != hipSuccess ||
+      (e = dalloc(w->allocs, &w->counters, 64)) != hipSuccess ||
+      (e = dalloc(w->allocs, &w->aux, (size_t)max_chains + 64)) != hipSuccess) {
+    free_all(w->allocs);
+    delete w;
+    return fail(MPG_ERR_HIP, std::string("mpg_workspace_create: ") + hipGetErrorString(e));
+  }
+  *out = w;
+  return MPG_OK;
+}
+extern "C" void mpg_workspace_destroy(mpg_workspace* w) {
+  if (!w) return;
+  free_all(w->allocs);
+  delete w;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+struct EpView {
+  const float* xD;
+  const float* nD;
+  const float* xL;
+  const uint8_t* len;
+  const uint8_t* type;
+  const int32_t* obj1;
+  int N;
+};
+__device__ __forceinline__ f3 ld_pt(const float* a, int N, int i) { return {a[i], a[N + i], a[2 * (size_t)N + i]}; }
+__device__ __forceinline__ bool finite3(f3 v) { return isfinite(v.x) && isfinite(v.y) && isfinite(v.z); }
+
+__device__ __forceinline__ Stack lane_stack(int depth) {
+  extern __shared__ int lds_stack[];
+  int lane = threadIdx.x & 63;
+  int wave = threadIdx.x >> 6;
+  return Stack{lds_stack + (size_t)wave * depth * 64 + lane, depth};
+}
+
+template <int N>
+__device__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
+                         uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
+                         Stack stk) {
+  int prim[N];
+  f3 pos[N];
+  int r = sample_seed<N>(S, G, P, E.type[c], E.obj1[c], ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), seed,
+                         (uint64_t)c, trial, alpha, prim, pos, stk);
+  st[c] = (int8_t)r;
+  const size_t NN = E.N;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim_out[i * NN + c] = r == 0 ? prim[i] : PRIM_NONE;
+    pos_out[(0 * KMAX + i) * NN + c] = r == 0 ? pos[i].x : 0.f;
+    pos_out[(1 * KMAX + i) * NN + c] = r == 0 ? pos[i].y : 0.f;
+    pos_out[(2 * KMAX + i) * NN + c] = r == 0 ? pos[i].z : 0.f;
+  }
+}
+
+__global__ void k_sample_seeds(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E, uint64_t seed,
+                               uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  int n = E.len[c];
+  if (n < 1 || n > KMAX || !finite3(ld_pt(E.xD, E.N, c)) || !finite3(ld_pt(E.nD, E.N, c))) {
+    st[c] = ST_BAD_INPUT;
+    return;
+  }
+  const DevGuide* g = has_guide ? &G : nullptr;
+  switch (n) {
+    case 1: seed_one<1>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 2: seed_one<2>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 3: seed_one<3>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 4: seed_one<4>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 5: seed_one<5>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 6: seed_one<6>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    case 7: seed_one<7>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+    default: seed_one<8>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
+  }
+}
+
+struct WalkIO {
+  const int32_t* seed_prim;
+  const float* seed_pos;
+  const int8_t* seed_status;
+  int32_t* prim_out;
+  float* pos_out;
+  int8_t* status;
+  uint8_t* iters;
+  uint64_t* sol;
+  float* G;
+  float* kappa;
+  float* resid;
+};
+
+template <int N>
+__device__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+                         Stack stk) {
+  const size_t NN = E.N;
+  int prim[N];
+  f3 x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim[i] = io.seed_prim[i * NN + c];
+    x[i] = {io.seed_pos[(0 * KMAX + i) * NN + c], io.seed_pos[(1 * KMAX + i) * NN + c],
+            io.seed_pos[(2 * KMAX + i) * NN + c]};
+  }
+  WalkOut R;
+  R.status = ST_SEED_INVALID;
+  R.iters = 0;
+  R.sol = 0;
+  R.G = 0.f;
+  R.kappa = 0.f;
+  R.resid = 0.f;
+  f3 xD = ld_pt(E.xD, E.N, c), xL = ld_pt(E.xL, E.N, c), nD = ld_pt(E.nD, E.N, c);
+  int type = E.type[c];
+  bool seed_ok = !(io.seed_status && io.seed_status[c] != 0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    bool inr = prim[i] >= 0 ? prim[i] < S.n_tris : (prim[i] != PRIM_NONE && -1 - prim[i] < S.n_spheres);
+    seed_ok = seed_ok && inr && finite3(x[i]);
+  }
+  if (seed_ok) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (((type >> i) & 1) && S.obj_info[prim_obj(S, prim[i])].x != MAT_DIELECTRIC) seed_ok = false;
+  }
+  if (seed_ok) {
+    int it = 0;
+    R.status = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
+    R.iters = it;
+    if (R.status == ST_CONVERGED) finish<N>(S, P, xD, nD, xL, type, prim, x, stk, R);
+    // ST_NEEDS_FP64 chains are finished by the FP64 pass
+  }
+  io.status[c] = (int8_t)R.status;
+  if (io.iters) io.iters[c] = (uint8_t)R.iters;
+  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
+  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
+  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
+  if (io.resid) io.resid[c] = R.resid;
+  bool have = seed_ok;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    io.prim_out[i * NN + c] = have ? prim[i] : PRIM_NONE;
+    io.pos_out[(0 * KMAX + i) * NN + c] = have ? x[i].x : 0.f;
+    io.pos_out[(1 * KMAX + i) * NN + c] = have ? x[i].y : 0.f;
+    io.pos_out[(2 * KMAX + i) * NN + c] = have ? x[i].z : 0.f;
+  }
+}
+
+template <int NMAX>
+__device__ __forceinline__ void walk_dispatch(const DevScene& S, const WalkParams& P, const EpView& E,
+                                              const WalkIO& io, int c, Stack stk) {
+  int n = E.len[c];
+  if (n < 1 || n > NMAX || !finite3(ld_pt(E.xD, E.N, c)) || !finite3(ld_pt(E.xL, E.N, c)) ||
+      !finite3(ld_pt(E.nD, E.N, c))) {
+    io.status[c] = ST_BAD_INPUT;
+    if (io.iters) io.iters[c] = 0;
+    if (io.sol) io.sol[c] = 0;
+    if (io.G) io.G[c] = 0.f;
+    if (io.kappa) io.kappa[c] = 0.f;
+    if (io.resid) io.resid[c] = 0.f;
+    return;
+  }
+  switch (n) {
+    case 1: walk_one<1>(S, P, E, io, c, stk); break;
+    case 2: if (NMAX >= 2) walk_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
+    case 3: if (NMAX >= 3) walk_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
+    case 4: if (NMAX >= 4) walk_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
+    case 5: if (NMAX >= 5) walk_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
+    case 6: if (NMAX >= 6) walk_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
+    case 7: if (NMAX >= 7) walk_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
+    default: if (NMAX >= 8) walk_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
+  }
+}
+
+// Plain form: one launch, one chain per lane, chains in input order; NMAX is
+// the longest chain the launch handles (the register budget follows it).
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_walk_plain(DevScene S, WalkParams P, EpView E, WalkIO io) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  walk_dispatch<NMAX>(S, P, E, io, c, stk);
+}
+
+// FP64 pass over the chains the walk left as ST_NEEDS_FP64.
+template <int N>
+__device__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+                         Stack stk) {
+  const size_t NN = E.N;
+  int prim[N];
+  f3 x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim[i] = io.prim_out[i * NN + c];
+    x[i] = {io.pos_out[(0 * KMAX + i) * NN + c], io.pos_out[(1 * KMAX + i) * NN + c],
+            io.pos_out[(2 * KMAX + i) * NN + c]};
+  }
+  WalkOut R;
+  R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
+  finish_fp64<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
+  io.status[c] = (int8_t)R.status;
+  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
+  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
+  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
+  if (io.resid) io.resid[c] = R.resid;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    io.pos_out[(0 * KMAX + i) * NN + c] = x[i].x;
+    io.pos_out[(1 * KMAX + i) * NN + c] = x[i].y;
+    io.pos_out[(2 * KMAX + i) * NN + c] = x[i].z;
+  }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_fp64_pass(DevScene S, WalkParams P, EpView E, WalkIO io) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  if (io.status[c] != ST_NEEDS_FP64) return;
+  int n = E.len[c];
+  switch (n) {
+    case 1: fp64_one<1>(S, P, E, io, c, stk); break;
+    case 2: if (NMAX >= 2) fp64_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
+    case 3: if (NMAX >= 3) fp64_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
+    case 4: if (NMAX >= 4) fp64_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
+    case 5: if (NMAX >= 5) fp64_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
+    case 6: if (NMAX >= 6) fp64_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
+    case 7: if (NMAX >= 7) fp64_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
+    default: if (NMAX >= 8) fp64_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
+  }
+}
+
+typedef void (*walk_kernel_t)(DevScene, WalkParams, EpView, WalkIO);
+static walk_kernel_t plain_kernel(int nmax) {
+  switch (nmax) {
+    case 1: return k_walk_plain<1>;
+    case 2: return k_walk_plain<2>;
+    case 3: return k_walk_plain<3>;
+    case 4: return k_walk_plain<4>;
+    case 5: return k_walk_plain<5>;
+    case 6: return k_walk_plain<6>;
+    case 7: return k_walk_plain<7>;
+    default: return k_walk_plain<8>;
+  }
+}
+static walk_kernel_t fp64_kernel(int nmax) {
+  switch (nmax) {
+    case 1: return k_fp64_pass<1>;
+    case 2: return k_fp64_pass<2>;
+    case 3: return k_fp64_pass<3>;
+    case 4: return k_fp64_pass<4>;
+    case 5: return k_fp64_pass<5>;
+    case 6: return k_fp64_pass<6>;
+    case 7: return k_fp64_pass<7>;
+    default: return k_fp64_pass<8>;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bernoulli trials (Sec. 5.8)
+// ---------------------------------------------------------------------------
+struct InvIO {
+  const int32_t* tprim;
+  const float* tpos;
+  const int8_t* tstatus;
+  int32_t* trials;
+  float* inv_prob;
+  uint8_t* truncated;
+  int max_trials, repeats;
+  uint64_t seed;
+  float alpha;
+};
+
+template <int N>
+__device__ void inv_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E,
+                        const InvIO& io, int c, Stack stk) {
+  const size_t NN = E.N;
+  f3 tx[N];
+  int tobj[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    tx[i] = {io.tpos[(0 * KMAX + i) * NN + c], io.tpos[(1 * KMAX + i) * NN + c], io.tpos[(2 * KMAX + i) * NN + c]};
+    tobj[i] = prim_obj(S, io.tprim[i * NN + c]);
+  }
+  f3 xD = ld_pt(E.xD, E.N, c), nD = ld_pt(E.nD, E.N, c), xL = ld_pt(E.xL, E.N, c);
+  int type = E.type[c], obj1 = E.obj1[c];
+  int total = 0;
+  bool trunc = false;
+  for (int r = 0; r < io.repeats; ++r) {
+    int K = io.max_trials;
+    bool found = false;
+    for (int k = 1; k <= io.max_trials && !found; ++k) {
+      uint64_t trial = 1 + (uint64_t)r * io.max_trials + (uint64_t)(k - 1);
+      int prim[N];
+      f3 x[N];
+      if (sample_seed<N>(S, G, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, prim, x, stk) != 0)
+        continue;
+      int it;
+      int ws = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
+      if (ws != ST_CONVERGED && ws != ST_NEEDS_FP64) continue;
+      bool m = true;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        f3 d = x[i] - tx[i];
+        m = m && prim_obj(S, prim[i]) == tobj[i] && dot(d, d) <= P.match2;
+      }
+      if (m) { K = k; found = true; }
+    }
+    if (!found) trunc = true;
+    total += K;
+  }
+  io.trials[c] = total;
+  io.inv_prob[c] = (float)total / (float)io.repeats;
+  if (io.truncated) io.truncated[c] = trunc ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E,
+                                                  InvIO io) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  int n = E.len[c];
+  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > KMAX || io.repeats < 1 || io.max_trials < 1) {
+    io.trials[c] = 0;
+    io.inv_prob[c] = 0.f;
+    if (io.truncated) io.truncated[c] = 0;
+    return;
+  }
+  const DevGuide* g = has_guide ? &G : nullptr;
+  switch (n) {
+    case 1: inv_one<1>(S, g, P, E, io, c, stk); break;
+    case 2: inv_one<2>(S, g, P, E, io, c, stk); break;
+    case 3: inv_one<3>(S, g, P, E, io, c, stk); break;
+    case 4: inv_one<4>(S, g, P, E, io, c, stk); break;
+    case 5: inv_one<5>(S, g, P, E, io, c, stk); break;
+    case 6: inv_one<6>(S, g, P, E, io, c, stk); break;
+    case 7: inv_one<7>(S, g, P, E, io, c, stk); break;
+    default: inv_one<8>(S, g, P, E, io, c, stk); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host entry points
+// ---------------------------------------------------------------------------
+static mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams* w, int* waves) {
+  if (!p) return fail(MPG_ERR_INVALID_ARG, "NULL walk params");
+  if (p->max_iter < 0 || p->max_iter > 255) return fail(MPG_ERR_INVALID_ARG, "max_iter outside 0..255");
+  if (!(p->scale > 0.0f)) return fail(MPG_ERR_INVALID_ARG, "scale must be positive");
+  if (!(p->tol_vertex >= 0.0f) || !(p->tol_residual >= 0.0f) || !(p->tmin_rel >= 0.0f) || !(p->match_rel >= 0.0f))
+    return fail(MPG_ERR_INVALID_ARG, "negative tolerance");
+  if (p->waves_per_group != 1 && p->waves_per_group != 2 && p->waves_per_group != 4)
+    return fail(MPG_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4");
+  int need = s->max_depth + 1;
+  int depth = p->stack_depth > 0 ? p->stack_depth : need;
+  if (depth < need) return fail(MPG_ERR_INVALID_ARG, "stack_depth below BVH depth + 1");
+  if ((size_t)p->waves_per_group * depth * 64 * 4 > 64 * 1024)
+    return fail(MPG_ERR_INVALID_ARG, "LDS stacks exceed 64 KiB per workgroup");
+  w->max_iter = p->max_iter;
+  float tv = p->tol_vertex * p->scale;
+  w->tol_step2 = tv * tv;
+  w->tol_residual = p->tol_residual;
+  w->tmin = p->tmin_rel * p->scale;
+  float m = p->match_rel * p->scale;
+  w->match2 = m * m;
+  w->fp64_cond = p->fp64_cond_threshold;
+  w->graze_cos = p->fp64_graze_cos;
+  w->cone_cos = p->cone_cos;
+  w->depth = depth;
+  *waves = p->waves_per_group;
+  if (p->max_len < 1 || p->max_len > KMAX) return fail(MPG_ERR_INVALID_ARG, "max_len outside 1..8");
+  return MPG_OK;
+}
+
+static mpg_status check_endpoints(const mpg_endpoints* e, EpView* v) {
+  if (!e) return fail(MPG_ERR_INVALID_ARG, "NULL endpoints");
+  if (e->N < 0) return fail(MPG_ERR_INVALID_ARG, "N < 0");
+  if (e->N > 0 && (!e->d_xD || !e->d_nD || !e->d_xL || !e->d_len || !e->d_type || !e->d_obj1))
+    return fail(MPG_ERR_INVALID_ARG, "NULL endpoint array");
+  v->xD = e->d_xD; v->nD = e->d_nD; v->xL = e->d_xL; v->len = e->d_len; v->type = e->d_type; v->obj1 = e->d_obj1;
+  v->N = e->N;
+  return MPG_OK;
+}
+
+extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const mpg_walk_params* p,
+                                   const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, float alpha,
+                                   mpg_chains* out, int8_t* d_status, void* stream) {
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: NULL scene");
+  WalkParams P;
+  int waves;
+  EpView E;
+  mpg_status st;
+  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
+  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
+  if (E.N == 0) return MPG_OK;
+  if (!out || !out->d_prim || !out->d_pos || !d_status) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: NULL output");
+  if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: alpha outside [0, 1]");
+  DevGuide G;
+  std::memset(&G, 0, sizeof(G));
+  if (g) G = g->dev();
+  int threads = 64 * waves;
+  size_t lds = (size_t)waves * P.depth * 64 * 4;
+  hipLaunchKernelGGL(k_sample_seeds, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
+                     s->dev, G, g ? 1 : 0, P, E, philox_seed, (uint64_t)trial, alpha, out->d_prim, out->d_pos,
+                     d_status);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
+                           int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream);
+
+extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
+                                          const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
+                                          const mpg_walk_out* wout, mpg_workspace* ws, void* stream) {
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: NULL scene");
+  WalkParams P;
+  int waves;
+  EpView E;
+  mpg_status st;
+  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
+  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
+  if (E.N == 0) return MPG_OK;
+  if (!seeds || !seeds->d_prim || !seeds->d_pos || !out || !out->d_prim || !out->d_pos || !wout || !wout->d_status)
+    return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: NULL chains or status");
+  WalkIO io;
+  io.seed_prim = seeds->d_prim; io.seed_pos = seeds->d_pos; io.seed_status = d_seed_status;
+  io.prim_out = out->d_prim; io.pos_out = out->d_pos;
+  io.status = wout->d_status; io.iters = wout->d_iters; io.sol = wout->d_solution_id;
+  io.G = wout->d_G; io.kappa = wout->d_kappa; io.resid = wout->d_residual;
+  if (p->form == MPG_FORM_PERSISTENT) {
+    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: workspace too small");
+    return walk_persistent(s, P, waves, p->bucketing, p->refill, p->max_len, E, io, ws, (hipStream_t)stream);
+  }
+  if (p->form != MPG_FORM_PLAIN) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: unknown form");
+  int threads = 64 * waves;
+  size_t lds = (size_t)waves * P.depth * 64 * 4;
+  dim3 grid((E.N + threads - 1) / threads);
+  hipLaunchKernelGGL(plain_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fp64_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, const mpg_walk_params* p,
+                                        const mpg_endpoints* ep, const mpg_chains* target,
+                                        const int8_t* d_target_status, int32_t max_trials, int32_t repeats,
+                                        uint64_t philox_seed, float alpha, int32_t* d_trials, float* d_inv_prob,
+                                        uint8_t* d_truncated, mpg_workspace* ws, void* stream) {
+  (void)ws;
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: NULL scene");
+  WalkParams P;
+  int waves;
+  EpView E;
+  mpg_status st;
+  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
+  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
+  if (E.N == 0) return MPG_OK;
+  if (!target || !target->d_prim || !target->d_pos || !d_target_status || !d_trials || !d_inv_prob)
+    return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: NULL argument");
+  if (max_trials < 0 || repeats < 0) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: negative trial count");
+  if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: alpha outside [0, 1]");
+  DevGuide G;
+  std::memset(&G, 0, sizeof(G));
+  if (g) G = g->dev();
+  InvIO io;
+  io.tprim = target->d_prim; io.tpos = target->d_pos; io.tstatus = d_target_status;
+  io.trials = d_trials; io.inv_prob = d_inv_prob; io.truncated = d_truncated;
+  io.max_trials = max_trials; io.repeats = repeats; io.seed = philox_seed; io.alpha = alpha;
+  int threads = 64 * waves;
+  size_t lds = (size_t)waves * P.depth * 64 * 4;
+  hipLaunchKernelGGL(k_inv_prob, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
+                     s->dev, G, g ? 1 : 0, P, E, io);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+// persistent form, guide fitting and the adjoint live in their own files
+#include "mpg_persistent.inc"
+#include "mpg_guide.inc"
+#include "mpg_adjoint.inc"
