@@ -1,0 +1,245 @@
+"""Benchmark: converged manifold walks/s on one MI355X.
+
+A step is one pass of the hot path over one batch of synthetic input:
+sample_seeds (p_0 / deduction) -> manifold_walk_batch (walk, FP32 finish) ->
+manifold_walk_fp64 (FP64 pass over near-singular / stalled / grazing chains).
+The default workload is the uneven batch: 2^23 chains of lengths 1..8
+(min(Geometric(0.4), 8)) through the four-slab stack plus a mirror sphere.
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  --gpus must be 1: this build runs
+on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 flops per unit of work (FMA = 2, add/mul/min/max/compare =
+# 1, sqrt/rcp/div = 1), counted from the kernel source.
+FLOPS_PER_UNIT = {
+    "box_tests": 25,               # one child box of a BVH node: 6 FMA + 12 min/max + 1 compare
+    "tri_tests": 79,               # watertight ray/triangle: shear 9 sub + 6 dot3, U/V/W, det, T, t
+    "sphere_tests": 30,            # closest-approach discriminant, roots, compares
+    "rays": 40,                    # per-ray set-up: axis choice, shear constants, reciprocal direction
+    "vertex_residual_evals": 175,  # primitive frame, blended normal, half vector, projections
+    "vertex_jacobian_evals": 540,  # + normal derivatives, 3 Jacobian blocks, block-Thomas step, back-substitution
+}
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="slab_uneven",
+                    choices=["sphere_mirror", "icosphere_tt", "water_caustic", "slab_uneven", "slab_adjoint"])
+    ap.add_argument("--n", type=int, default=None, help="chains (default: the workload's size)")
+    ap.add_argument("--form", default="persistent", choices=["plain", "persistent"])
+    ap.add_argument("--compare-forms", type=int, default=1, help="also time the other form (fewer steps)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2311_12818_amd", "tuned.json"))
+    return ap.parse_args()
+
+
+DEFAULT_N = {"sphere_mirror": 4096, "icosphere_tt": 1 << 20, "water_caustic": 1 << 22, "slab_uneven": 1 << 23,
+             "slab_adjoint": 1 << 20}
+MAX_LEN = {"sphere_mirror": 1, "icosphere_tt": 2, "water_caustic": 1, "slab_uneven": 8, "slab_adjoint": 4}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2311_12818_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_tuned(path, workload):
+    try:
+        with open(path) as fh:
+            return json.load(fh).get(workload, {})
+    except (OSError, ValueError):
+        return {}
+
+
+def cpu_baseline(name, sc, ep_fn, n_total, seconds):
+    import numpy as np
+
+    import oracle as O
+    import workloads as W
+    threads = min(16, os.cpu_count() or 1)
+    osc = O.Scene(sc)
+    prm = O.params(sc.scale, cone_cos=math.cos(math.radians(W.SEED_CONE_DEG)))
+    full = ep_fn(min(n_total, 1 << 20))
+    chunk = 8192
+    done, conv, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds and done < full.n:
+        idx = np.arange(done, min(done + chunk, full.n))
+        ep = full.subset(idx)
+        prim, pos, st = O.sample_seeds(osc, ep, prm=prm, nthreads=threads)
+        r = O.walk(osc, ep, prim, pos.astype(np.float32), st, prm=prm, nthreads=threads)
+        conv += int((r["status"] == O.CONVERGED).sum())
+        done += len(idx)
+    el = time.perf_counter() - t0
+    return {"value": conv / el, "unit": "converged walks/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} configurations of the same {name} batch (oracle p_0 seeds + FP64 walk + polish, "
+                      f"{el:.1f} s on {threads} threads)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2311_12818_amd as M
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    name = args.workload
+    scene_fn, ep_fn = W.WORKLOADS[name]
+    N = args.n or DEFAULT_N[name]
+    sc = scene_fn()
+    ep = ep_fn(N)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    tuned = load_tuned(args.tuned, name)
+    cone = math.cos(math.radians(W.SEED_CONE_DEG))
+
+    def params(form):
+        kw = dict(cone_cos=cone, max_len=MAX_LEN[name], defer_fp64=1,
+                  form=M.FORM_PERSISTENT if form == "persistent" else M.FORM_PLAIN)
+        if form == "persistent":
+            for k in ("bucketing", "waves_per_group", "stack_depth", "refill"):
+                if k in tuned:
+                    kw[k] = int(tuned[k])
+        return M.walk_params(sc.scale, **kw)
+
+    ws = M.Workspace(N)
+    prim, pos = M.empty_chains(N)
+    outs = M.walk_outputs(N)
+    stream = torch.cuda.current_stream()
+
+    def step(prm):
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+        M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+        return st
+
+    def timed(form, steps, warmup):
+        prm = params(form)
+        for _ in range(warmup):
+            step(prm)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            e = ev[k]
+            e[0].record(stream)
+            p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+            e[1].record(stream)
+            M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+            e[2].record(stream)
+            M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+            e[3].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        seeds_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+        walk_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+        fp64_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+        st = outs["status"].cpu().numpy()
+        return dict(wall=wall, ms_per_step=1e3 * wall / steps, seeds_ms=seeds_ms, walk_ms=walk_ms, fp64_ms=fp64_ms,
+                    status=st)
+
+    main_form = args.form
+    R = timed(main_form, args.steps, args.warmup)
+    lengths = ep.length
+    conv = R["status"] == M.CONVERGED
+    n_conv = int(conv.sum())
+    value = n_conv / (R["ms_per_step"] / 1e3)
+    per_k = {}
+    for k in range(1, 9):
+        m = lengths == k
+        if m.any():
+            per_k[str(k)] = {"chains": int(m.sum()), "converged": int((conv & m).sum()),
+                             "converged_walks_per_s": float((conv & m).sum() / (R["ms_per_step"] / 1e3))}
+    forms = {main_form: {"converged_walks_per_s": value, "ms_per_step": R["ms_per_step"], "walk_kernel_ms": R["walk_ms"],
+                         "seeds_ms": R["seeds_ms"], "fp64_pass_ms": R["fp64_ms"]}}
+    if args.compare_forms:
+        other = "plain" if main_form == "persistent" else "persistent"
+        try:
+            R2 = timed(other, max(1, args.steps // 2), 1)
+            c2 = int((R2["status"] == M.CONVERGED).sum())
+            forms[other] = {"converged_walks_per_s": c2 / (R2["ms_per_step"] / 1e3), "ms_per_step": R2["ms_per_step"],
+                            "walk_kernel_ms": R2["walk_ms"], "seeds_ms": R2["seeds_ms"], "fp64_pass_ms": R2["fp64_ms"],
+                            "converged_agree_with_main_form": float((R2["status"] == R["status"]).mean())}
+        except M.MPGError as exc:
+            forms[other] = {"error": str(exc)}
+
+    # untimed counting pass: algorithmic work of one walk launch
+    prm_c = params("plain")
+    p, q, st = M.sample_seeds(scene, dep, prm_c)
+    _, _, outs_c, counts = M.walk_count(scene, prm_c, dep, p, q, st)
+    flops = sum(FLOPS_PER_UNIT[k] * counts[k] for k in FLOPS_PER_UNIT)
+    walk_s = R["walk_ms"] / 1e3
+    achieved = flops / walk_s / 1e12
+    # algorithmic HBM bytes of the walk launch: endpoints (38 B), seed chain in
+    # (16 B per vertex), chain out (16 B per vertex), per-chain outputs (22 B)
+    verts = int(lengths.sum())
+    hbm_bytes = 60 * N + 32 * verts
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{name}_{main_form}.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                "kernel": "walk (persistent)" if main_form == "persistent" else "walk (plain)",
+                "flops_per_launch": flops, "counts_per_launch": counts,
+                "hbm_algorithmic_GBs": hbm_bytes / walk_s / 1e9}
+
+    out = {
+        "metric": "converged manifold walks/s (k=1..8) at 1e-4 vertex tol; plain vs batched vs +adjoint",
+        "value": value,
+        "unit": "converged walks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "chains": N, "scene_tris": int(sc.n_tris), "max_len": MAX_LEN[name],
+                   "form": main_form, "converged_fraction": n_conv / N, "tuned": tuned},
+        "per_k": per_k,
+        "forms": forms,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(name, sc, ep_fn, N, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

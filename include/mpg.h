@@ -52,6 +52,7 @@ typedef int32_t mpg_status;
 #define MPG_SEED_INVALID 5  /* the seed could not be drawn or deduced */
 #define MPG_FP64_REJECT 6   /* near-singular chain failed the FP64 residual check */
 #define MPG_BAD_INPUT 7     /* non-finite endpoint or chain length outside 1..8 */
+#define MPG_NEEDS_FP64 8    /* converged in FP32, awaiting manifold_walk_fp64 (defer_fp64 only) */
 
 #define MPG_MAT_MIRROR 0
 #define MPG_MAT_DIELECTRIC 1
@@ -167,6 +168,7 @@ typedef struct {
   int32_t stack_depth;       /* LDS traversal stack entries per lane (>= BVH depth + 1; 0 = automatic) */
   int32_t refill;            /* persistent form: lanes pull a new chain as soon as theirs finishes (1) */
   int32_t max_len;           /* longest chain in the batch (1..8, default 8); longer chains get MPG_BAD_INPUT */
+  int32_t defer_fp64;        /* 1: leave MPG_NEEDS_FP64 chains for a later manifold_walk_fp64 call (0) */
 } mpg_walk_params;
 
 /* Fills defaults for a scene of scale L. */
@@ -230,6 +232,24 @@ mpg_status sample_seeds(const mpg_scene* scene, const mpg_guide* guide, const mp
 mpg_status manifold_walk_batch(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
                                const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
                                const mpg_walk_out* wout, mpg_workspace* ws, void* hip_stream);
+
+/* FP64 pass of the walk (normally run by manifold_walk_batch itself): chains
+ * whose status is MPG_NEEDS_FP64 (converged in FP32 but near-singular, stalled
+ * at the FP32 residual floor, or scattering within fp64_graze_cos of grazing)
+ * get an FP64 residual check with up to two FP64 Newton steps inside their
+ * primitives, then their side / visibility tests, G and kappa in FP64.  The
+ * chain arrays are read and updated in place.  Other chains are untouched. */
+mpg_status manifold_walk_fp64(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
+                              mpg_chains* chains, const mpg_walk_out* wout, void* hip_stream);
+
+/* Profiling variant of the plain walk (FP64 pass included): same outputs as
+ * manifold_walk_batch, plus work tallies reduced into d_counts[8] (device,
+ * uint64): BVH box tests, triangle tests, sphere tests, rays, residual-only
+ * vertex evaluations, Jacobian vertex evaluations, FP64 Jacobian vertex
+ * evaluations, chains.  The counters cost time: do not time this call. */
+mpg_status mpg_walk_count(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
+                          const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
+                          const mpg_walk_out* wout, uint64_t* d_counts, void* hip_stream);
 
 /* Reciprocal probability by repeated independent trials (Sec. 5.8): for each
  * target with status MPG_CONVERGED, seeds are redrawn from the same

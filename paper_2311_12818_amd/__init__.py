@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmpg.so")
 KMAX = 8
 PRIM_NONE = -2 ** 31
 
-CONVERGED, MAX_ITER, SINGULAR, SIDE_INVALID, OCCLUDED, SEED_INVALID, FP64_REJECT, BAD_INPUT = range(8)
+CONVERGED, MAX_ITER, SINGULAR, SIDE_INVALID, OCCLUDED, SEED_INVALID, FP64_REJECT, BAD_INPUT, NEEDS_FP64 = range(9)
 STATUS_NAMES = ["converged", "max_iter", "singular", "side_invalid", "occluded", "seed_invalid", "fp64_reject",
                 "bad_input"]
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
@@ -67,7 +67,7 @@ class mpg_walk_params(C.Structure):
     _fields_ = [("max_iter", I32), ("tol_vertex", F32), ("tol_residual", F32), ("scale", F32), ("tmin_rel", F32),
                 ("match_rel", F32), ("fp64_cond_threshold", F32), ("fp64_graze_cos", F32), ("cone_cos", F32), ("form", I32),
                 ("bucketing", I32), ("waves_per_group", I32), ("stack_depth", I32), ("refill", I32),
-                ("max_len", I32)]
+                ("max_len", I32), ("defer_fp64", I32)]
 
 
 class mpg_guide_desc(C.Structure):
@@ -102,11 +102,16 @@ def lib():
         L.estimate_inv_prob.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                         C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, F32, P, P, P, P, P]
         L.fit_guide.argtypes = [P, P, I32, P, P, P]
+        L.manifold_walk_fp64.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                         C.POINTER(mpg_chains), C.POINTER(mpg_walk_out), P]
+        L.mpg_walk_count.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.POINTER(mpg_chains),
+                                     P, C.POINTER(mpg_chains), C.POINTER(mpg_walk_out), P, P]
         L.manifold_walk_adjoint.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                             C.POINTER(mpg_chains), P, P, P, P, P, P, P]
         for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
-                     "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint"]:
+                     "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
+                     "manifold_walk_fp64", "mpg_walk_count"]:
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -303,6 +308,37 @@ def manifold_walk_batch(scene: Scene, params: mpg_walk_params, ep: Endpoints, se
                                      C.byref(oc), C.byref(wo), ws.h if ws else None, _stream()),
            "manifold_walk_batch")
     return out_prim, out_pos, outs
+
+
+def _wout(outs):
+    return mpg_walk_out(outs["status"].data_ptr(), outs["iters"].data_ptr(), outs["sol"].data_ptr(),
+                        outs["G"].data_ptr(), outs["kappa"].data_ptr(), outs["residual"].data_ptr())
+
+
+def manifold_walk_fp64(scene: Scene, params: mpg_walk_params, ep: Endpoints, prim, pos, outs):
+    """FP64 pass over chains left as NEEDS_FP64 by a deferred walk (in place)."""
+    ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
+    _check(lib().manifold_walk_fp64(scene.h, C.byref(params), C.byref(ep.c()), C.byref(ch), C.byref(_wout(outs)),
+                                    _stream()), "manifold_walk_fp64")
+    return prim, pos, outs
+
+
+COUNT_NAMES = ["box_tests", "tri_tests", "sphere_tests", "rays", "vertex_residual_evals", "vertex_jacobian_evals",
+               "vertex_jacobian_evals_fp64", "chains"]
+
+
+def walk_count(scene: Scene, params: mpg_walk_params, ep: Endpoints, seed_prim, seed_pos, seed_status=None):
+    """Untimed counting walk: returns (prim, pos, outputs, work tallies dict)."""
+    torch = _torch()
+    out_prim, out_pos = empty_chains(ep.N, ep.xD.device)
+    outs = walk_outputs(ep.N, ep.xD.device)
+    counts = torch.zeros(8, dtype=torch.int64, device=ep.xD.device)
+    seeds = mpg_chains(seed_prim.data_ptr(), seed_pos.data_ptr())
+    oc = mpg_chains(out_prim.data_ptr(), out_pos.data_ptr())
+    _check(lib().mpg_walk_count(scene.h, C.byref(params), C.byref(ep.c()), C.byref(seeds), _ptr(seed_status),
+                                C.byref(oc), C.byref(_wout(outs)), counts.data_ptr(), _stream()), "mpg_walk_count")
+    torch.cuda.synchronize()
+    return out_prim, out_pos, outs, dict(zip(COUNT_NAMES, [int(v) for v in counts.cpu().tolist()]))
 
 
 def estimate_inv_prob(scene: Scene, params: mpg_walk_params, ep: Endpoints, tprim, tpos, tstatus, max_trials=64,

@@ -153,9 +153,31 @@ struct Hit {
 };
 
 // Lane-private traversal stack in LDS: entry k of lane l at base[k * 64].
+// The work tallies are empty here; CountStack below carries real counters
+// for the untimed counting launch (every device routine that does counted
+// work is templated on the stack type, so the timed kernels carry none).
 struct Stack {
   int* base;
   int depth;
+  __device__ __forceinline__ void box(int) {}
+  __device__ __forceinline__ void tri() {}
+  __device__ __forceinline__ void sph() {}
+  __device__ __forceinline__ void ray() {}
+  __device__ __forceinline__ void vc() {}
+  __device__ __forceinline__ void vj() {}
+  __device__ __forceinline__ void vj64() {}
+};
+struct CountStack {
+  int* base;
+  int depth;
+  uint32_t nbox, ntri, nsph, nray, nvc, nvj, nvj64;
+  __device__ __forceinline__ void box(int k) { nbox += k; }
+  __device__ __forceinline__ void tri() { ++ntri; }
+  __device__ __forceinline__ void sph() { ++nsph; }
+  __device__ __forceinline__ void ray() { ++nray; }
+  __device__ __forceinline__ void vc() { ++nvc; }
+  __device__ __forceinline__ void vj() { ++nvj; }
+  __device__ __forceinline__ void vj64() { ++nvj64; }
 };
 
 __device__ __forceinline__ void take(Hit& h, int prim, float t) {
@@ -169,10 +191,13 @@ __device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k ==
 
 // Returns false only on stack overflow (the library sizes stacks so that it
 // cannot happen).  h.prim == PRIM_NONE when nothing was hit.
-__device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& h, Stack stk) {
+template <class STK>
+__device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& h, STK& stk) {
   h.t = INFINITY;
   h.prim = PRIM_NONE;
+  stk.ray();
   for (int s = 0; s < S.n_spheres; ++s) {
+    stk.sph();
     float4 sp = S.spheres[s];
     int prim = -1 - s;
     f3 oc = o - ld3(sp);
@@ -215,6 +240,7 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
   int ref = 0;
   for (;;) {
     if (ref >= 0) {
+      stk.box(2);
       const float4* nd = S.nodes + 4 * (size_t)ref;
       float4 a = nd[0], b = nd[1], c = nd[2];
       int4 ch = *reinterpret_cast<const int4*>(nd + 3);
@@ -247,6 +273,7 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
         float4 v0 = S.tri_v[3 * (size_t)k], v1 = S.tri_v[3 * (size_t)k + 1], v2 = S.tri_v[3 * (size_t)k + 2];
         int prim = __float_as_int(v0.w);
         if (prim == excl) continue;
+        stk.tri();
         f3 A = ld3(v0) - o, B = ld3(v1) - o, C = ld3(v2) - o;
         float Ax = dot(rx, A), Ay = dot(ry, A), Bx = dot(rx, B), By = dot(ry, B), Cx = dot(rx, C), Cy = dot(ry, C);
         float U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
@@ -454,9 +481,9 @@ struct Sweep {
 // fly (block Thomas: D~_i = D_i - L_i G_{i-1}, r~_i = -C_i - L_i g_{i-1},
 // G_i = D~_i^-1 U_i, g_i = D~_i^-1 r~_i), then back-substitute
 // y_n = g_n, y_i = g_i - G_i y_{i+1}.  JAC = false evaluates C only.
-template <typename T, int N, bool JAC>
+template <typename T, int N, bool JAC, class STK>
 __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL, int type, const int* prim,
-                                      const vec3<T>* x, Sweep<T, N>& W) {
+                                      const vec3<T>* x, Sweep<T, N>& W, STK& stk) {
   T g[N][2];
   W.c2 = 0;
   W.cinf = 0;
@@ -475,6 +502,9 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
     T ea, eb;
     vertex_etas(gc, (type >> i) & 1, xp, ea, eb);
     VJ<T> v;
+    if (!JAC) stk.vc();
+    else if (sizeof(T) == 4) stk.vj();
+    else stk.vj64();
     vertex_cj<T, JAC>(gc, xp, xn, ea, eb, pe1, pe2, N > 1 && i < N - 1 ? gn.e1 : gc.e1,
                       N > 1 && i < N - 1 ? gn.e2 : gc.e2, v);
     W.c2 += v.C0 * v.C0 + v.C1 * v.C1;
@@ -535,9 +565,9 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
 // Reprojection: for i = 1..n in order, cast from the moved previous vertex
 // (x_0 = x_D) toward the displaced vertex i; the first hit must lie on vertex
 // i's object.
-template <int N>
+template <int N, class STK>
 __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x, const f3* dl, float beta,
-                                          const int* obj, float tmin, Stack stk, f3* xn, int* pn) {
+                                          const int* obj, float tmin, STK& stk, f3* xn, int* pn) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     f3 o = i == 0 ? xD : xn[i > 0 ? i - 1 : 0];
@@ -564,14 +594,14 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
 // |C|_2 decreases (then beta = min(1, 2 length)); a rejected full step that
 // was within tol_vertex L ends the walk as ST_NEEDS_FP64 (precision floor);
 // any other rejection sets beta = length / 2.
-template <int N>
+template <int N, class STK>
 __device__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type, int* prim, f3* x,
-                         int& iters, Stack stk) {
+                         int& iters, STK& stk) {
   int obj[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) obj[i] = prim_obj(S, prim[i]);
   Sweep<float, N> W;
-  sweep<float, N, true>(S, xD, xL, type, prim, x, W);
+  sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
   iters = 0;
   if (W.singular) return ST_SINGULAR;
   float beta = 1.0f;
@@ -590,13 +620,13 @@ __device__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, i
       continue;
     }
     Sweep<float, N> Wc;
-    sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc);
+    sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc, stk);
     bool done = small && Wc.cinf <= P.tol_residual;
     if (done || Wc.c2 < c2) {
 #pragma unroll
       for (int i = 0; i < N; ++i) { x[i] = xn[i]; prim[i] = pn[i]; }
       if (done) return ST_CONVERGED;
-      sweep<float, N, true>(S, xD, xL, type, prim, x, W);
+      sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
       if (W.singular) return ST_SINGULAR;
       c2 = W.c2;
       step2 = 0.0f;
@@ -631,11 +661,11 @@ __device__ __forceinline__ float fresnel(float cos_i, float eta_i, float eta_t) 
 // FP64 at the FP32 vertices and take up to two FP64 Newton steps inside the
 // current primitives (planar for triangles, radial projection for spheres).
 // On success xd holds the FP64 vertices and W their FP64 Jacobian sweep.
-template <int N>
+template <int N, class STK>
 __device__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int type, const int* prim, d3* xd,
-                           Sweep<double, N>& W, float& resid) {
+                           Sweep<double, N>& W, float& resid, STK& stk) {
   for (int k = 0; k < 2; ++k) {
-    sweep<double, N, true>(S, xD, xL, type, prim, xd, W);
+    sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk);
     if (W.cinf < 1e-12 || W.singular) break;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -648,7 +678,7 @@ __device__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int type, const int*
       xd[i] = nx;
     }
   }
-  sweep<double, N, true>(S, xD, xL, type, prim, xd, W);
+  sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk);
   resid = (float)W.cinf;
   return W.cinf < 1e-6 && !W.singular;
 }
@@ -683,9 +713,9 @@ __device__ __forceinline__ double fresnel_t(double cos_i, double eta_i, double e
   return 0.5 * (rs * rs + rp * rp);
 }
 
-template <typename T, int N>
+template <typename T, int N, class STK>
 __device__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, vec3<T> nD, vec3<T> xL, int type,
-                            const int* prim, const vec3<T>* x, const Sweep<T, N>& W, Stack stk, WalkOut& R) {
+                            const int* prim, const vec3<T>* x, const Sweep<T, N>& W, STK& stk, WalkOut& R) {
   T kappa = 1;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -743,32 +773,32 @@ __device__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, 
 // condition estimate exceeds fp64_cond, or that scatter within graze_cos of
 // grazing (where the FP32 Jacobian entries cancel) are left as ST_NEEDS_FP64
 // for the FP64 pass; the others are finished in FP32.
-template <int N>
+template <int N, class STK>
 __device__ void finish(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
-                       const f3* x, Stack stk, WalkOut& R) {
+                       const f3* x, STK& stk, WalkOut& R) {
   Sweep<float, N> W;
-  sweep<float, N, true>(S, xD, xL, type, prim, x, W);
+  sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
   R.resid = W.cinf;
   if (W.singular || !(W.cond <= P.fp64_cond) || !(W.cmin >= P.graze_cos)) { R.status = ST_NEEDS_FP64; return; }
-  finish_with<float, N>(S, P, xD, nD, xL, type, prim, x, W, stk, R);
+  finish_with<float, N, STK>(S, P, xD, nD, xL, type, prim, x, W, stk, R);
 }
 
 // FP64 pass for one flagged chain: FP64 residual check and polish, then the
 // side / visibility tests, kappa and G in FP64.
-template <int N>
+template <int N, class STK>
 __device__ void finish_fp64(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
-                            f3* x, Stack stk, WalkOut& R) {
+                            f3* x, STK& stk, WalkOut& R) {
   d3 xd[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) xd[i] = cvt<double>(x[i]);
   Sweep<double, N> W;
   float r64;
-  bool ok = fp64_check<N>(S, cvt<double>(xD), cvt<double>(xL), type, prim, xd, W, r64);
+  bool ok = fp64_check<N>(S, cvt<double>(xD), cvt<double>(xL), type, prim, xd, W, r64, stk);
   R.resid = r64;
   if (!ok) { R.status = ST_FP64_REJECT; return; }
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = cvt<float>(xd[i]);
-  finish_with<double, N>(S, P, cvt<double>(xD), cvt<double>(nD), cvt<double>(xL), type, prim, xd, W, stk, R);
+  finish_with<double, N, STK>(S, P, cvt<double>(xD), cvt<double>(nD), cvt<double>(xL), type, prim, xd, W, stk, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,8 +871,9 @@ __device__ bool p0_point(const DevScene& S, const WalkParams& P, int obj1, f3 xD
   return true;
 }
 
+template <class STK>
 __device__ bool guided_point(const DevScene& S, const DevGuide& G, int cell, uint64_t seed, uint64_t chain,
-                             uint64_t trial, const U8& U0, Stack stk, f3& pt) {
+                             uint64_t trial, const U8& U0, STK& stk, f3& pt) {
   const int K = G.comps;
   for (int attempt = 0; attempt <= 8; ++attempt) {
     U8 U = attempt == 0 ? U0 : philox_uniforms(seed, chain, trial, (uint64_t)attempt);
@@ -872,10 +903,10 @@ __device__ bool guided_point(const DevScene& S, const DevGuide& G, int cell, uin
 }
 
 // One seed chain of length N.  Returns 0 or ST_SEED_INVALID.
-template <int N>
+template <int N, class STK>
 __device__ int sample_seed(const DevScene& S, const DevGuide* G, const WalkParams& P, int type, int obj1, f3 xD,
                            f3 nD, uint64_t seed, uint64_t chain, uint64_t trial, float alpha, int* prim, f3* pos,
-                           Stack stk) {
+                           STK& stk) {
   U8 U = philox_uniforms(seed, chain, trial, 0);
   f3 pt;
   bool ok = false;

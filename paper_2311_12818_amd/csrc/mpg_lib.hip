@@ -277,6 +277,7 @@ extern "C" mpg_status mpg_walk_params_default(float scale, mpg_walk_params* p) {
   p->stack_depth = 0;
   p->refill = 1;
   p->max_len = KMAX;
+  p->defer_fp64 = 0;
   return MPG_OK;
 }
 
@@ -326,10 +327,10 @@ __device__ __forceinline__ Stack lane_stack(int depth) {
   return Stack{lds_stack + (size_t)wave * depth * 64 + lane, depth};
 }
 
-template <int N>
+template <int N, class STK>
 __device__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
                          uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
-                         Stack stk) {
+                         STK& stk) {
   int prim[N];
   f3 pos[N];
   int r = sample_seed<N>(S, G, P, E.type[c], E.obj1[c], ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), seed,
@@ -382,9 +383,9 @@ struct WalkIO {
   float* resid;
 };
 
-template <int N>
+template <int N, class STK>
 __device__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
-                         Stack stk) {
+                         STK& stk) {
   const size_t NN = E.N;
   int prim[N];
   f3 x[N];
@@ -437,9 +438,9 @@ __device__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E
   }
 }
 
-template <int NMAX>
+template <int NMAX, class STK>
 __device__ __forceinline__ void walk_dispatch(const DevScene& S, const WalkParams& P, const EpView& E,
-                                              const WalkIO& io, int c, Stack stk) {
+                                              const WalkIO& io, int c, STK& stk) {
   int n = E.len[c];
   if (n < 1 || n > NMAX || !finite3(ld_pt(E.xD, E.N, c)) || !finite3(ld_pt(E.xL, E.N, c)) ||
       !finite3(ld_pt(E.nD, E.N, c))) {
@@ -474,9 +475,9 @@ __global__ void __launch_bounds__(256) k_walk_plain(DevScene S, WalkParams P, Ep
 }
 
 // FP64 pass over the chains the walk left as ST_NEEDS_FP64.
-template <int N>
+template <int N, class STK>
 __device__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
-                         Stack stk) {
+                         STK& stk) {
   const size_t NN = E.N;
   int prim[N];
   f3 x[N];
@@ -521,7 +522,62 @@ __global__ void __launch_bounds__(256) k_fp64_pass(DevScene S, WalkParams P, EpV
   }
 }
 
+// Counting launch: the plain walk with every unit of work tallied per lane
+// (box tests, triangle tests, sphere tests, rays, residual-only and Jacobian
+// vertex evaluations, FP64 vertex evaluations); the tallies are reduced into
+// counts[0..6], counts[7] = chains.  Used untimed to obtain the algorithmic
+// work of a launch.
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_walk_count(DevScene S, WalkParams P, EpView E, WalkIO io,
+                                                    unsigned long long* counts) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack base = lane_stack(P.depth);
+  CountStack stk{base.base, base.depth, 0, 0, 0, 0, 0, 0, 0};
+  if (c < E.N) walk_dispatch<NMAX>(S, P, E, io, c, stk);
+  if (c < E.N && io.status[c] == ST_NEEDS_FP64) {
+    int n = E.len[c];
+    switch (n) {
+      case 1: fp64_one<1>(S, P, E, io, c, stk); break;
+      case 2: if (NMAX >= 2) fp64_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
+      case 3: if (NMAX >= 3) fp64_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
+      case 4: if (NMAX >= 4) fp64_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
+      case 5: if (NMAX >= 5) fp64_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
+      case 6: if (NMAX >= 6) fp64_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
+      case 7: if (NMAX >= 7) fp64_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
+      default: if (NMAX >= 8) fp64_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
+    }
+  }
+  if (c < E.N) {
+    atomicAdd(&counts[0], (unsigned long long)stk.nbox);
+    atomicAdd(&counts[1], (unsigned long long)stk.ntri);
+    atomicAdd(&counts[2], (unsigned long long)stk.nsph);
+    atomicAdd(&counts[3], (unsigned long long)stk.nray);
+    atomicAdd(&counts[4], (unsigned long long)stk.nvc);
+    atomicAdd(&counts[5], (unsigned long long)stk.nvj);
+    atomicAdd(&counts[6], (unsigned long long)stk.nvj64);
+    atomicAdd(&counts[7], 1ULL);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ULL;
+}
+
 typedef void (*walk_kernel_t)(DevScene, WalkParams, EpView, WalkIO);
+typedef void (*count_kernel_t)(DevScene, WalkParams, EpView, WalkIO, unsigned long long*);
+static count_kernel_t count_kernel(int nmax) {
+  switch (nmax) {
+    case 1: return k_walk_count<1>;
+    case 2: return k_walk_count<2>;
+    case 3: return k_walk_count<3>;
+    case 4: return k_walk_count<4>;
+    case 5: return k_walk_count<5>;
+    case 6: return k_walk_count<6>;
+    case 7: return k_walk_count<7>;
+    default: return k_walk_count<8>;
+  }
+}
 static walk_kernel_t plain_kernel(int nmax) {
   switch (nmax) {
     case 1: return k_walk_plain<1>;
@@ -562,9 +618,9 @@ struct InvIO {
   float alpha;
 };
 
-template <int N>
+template <int N, class STK>
 __device__ void inv_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E,
-                        const InvIO& io, int c, Stack stk) {
+                        const InvIO& io, int c, STK& stk) {
   const size_t NN = E.N;
   f3 tx[N];
   int tobj[N];
@@ -718,17 +774,77 @@ extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_par
   io.prim_out = out->d_prim; io.pos_out = out->d_pos;
   io.status = wout->d_status; io.iters = wout->d_iters; io.sol = wout->d_solution_id;
   io.G = wout->d_G; io.kappa = wout->d_kappa; io.resid = wout->d_residual;
-  if (p->form == MPG_FORM_PERSISTENT) {
-    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: workspace too small");
-    return walk_persistent(s, P, waves, p->bucketing, p->refill, p->max_len, E, io, ws, (hipStream_t)stream);
-  }
-  if (p->form != MPG_FORM_PLAIN) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: unknown form");
   int threads = 64 * waves;
   size_t lds = (size_t)waves * P.depth * 64 * 4;
   dim3 grid((E.N + threads - 1) / threads);
-  hipLaunchKernelGGL(plain_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
-  HIP_TRY(hipGetLastError());
+  if (p->form == MPG_FORM_PERSISTENT) {
+    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: workspace too small");
+    mpg_status st2 = walk_persistent(s, P, waves, p->bucketing, p->refill, p->max_len, E, io, ws, (hipStream_t)stream);
+    if (st2 != MPG_OK) return st2;
+  } else if (p->form == MPG_FORM_PLAIN) {
+    hipLaunchKernelGGL(plain_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
+    HIP_TRY(hipGetLastError());
+  } else {
+    return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: unknown form");
+  }
+  if (p->defer_fp64) return MPG_OK;
   hipLaunchKernelGGL(fp64_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+static mpg_status walk_io(const mpg_chains* chains, const mpg_walk_out* wout, WalkIO* io) {
+  if (!chains || !chains->d_prim || !chains->d_pos || !wout || !wout->d_status)
+    return fail(MPG_ERR_INVALID_ARG, "NULL chains or status");
+  io->seed_prim = chains->d_prim; io->seed_pos = chains->d_pos; io->seed_status = nullptr;
+  io->prim_out = chains->d_prim; io->pos_out = chains->d_pos;
+  io->status = wout->d_status; io->iters = wout->d_iters; io->sol = wout->d_solution_id;
+  io->G = wout->d_G; io->kappa = wout->d_kappa; io->resid = wout->d_residual;
+  return MPG_OK;
+}
+
+extern "C" mpg_status manifold_walk_fp64(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
+                                         mpg_chains* chains, const mpg_walk_out* wout, void* stream) {
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_fp64: NULL scene");
+  WalkParams P;
+  int waves;
+  EpView E;
+  WalkIO io;
+  mpg_status st;
+  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
+  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
+  if (E.N == 0) return MPG_OK;
+  if ((st = walk_io(chains, wout, &io)) != MPG_OK) return st;
+  int threads = 64 * waves;
+  size_t lds = (size_t)waves * P.depth * 64 * 4;
+  hipLaunchKernelGGL(fp64_kernel(p->max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds,
+                     (hipStream_t)stream, s->dev, P, E, io);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+extern "C" mpg_status mpg_walk_count(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
+                                     const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
+                                     const mpg_walk_out* wout, uint64_t* d_counts, void* stream) {
+  if (!s) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL scene");
+  WalkParams P;
+  int waves;
+  EpView E;
+  WalkIO io;
+  mpg_status st;
+  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
+  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
+  if (!d_counts) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL counts");
+  if ((st = walk_io(out, wout, &io)) != MPG_OK) return st;
+  if (!seeds || !seeds->d_prim || !seeds->d_pos) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL seeds");
+  io.seed_prim = seeds->d_prim; io.seed_pos = seeds->d_pos; io.seed_status = d_seed_status;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)stream, (unsigned long long*)d_counts, 8);
+  HIP_TRY(hipGetLastError());
+  if (E.N == 0) return MPG_OK;
+  int threads = 64 * waves;
+  size_t lds = (size_t)waves * P.depth * 64 * 4;
+  hipLaunchKernelGGL(count_kernel(p->max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds,
+                     (hipStream_t)stream, s->dev, P, E, io, (unsigned long long*)d_counts);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }

@@ -73,7 +73,7 @@ def test_walk_parity_on_oracle_seeds(mpg, name, n, max_len):
     # finished in FP64; FP32 vertex errors <= 1e-5 over segments of length
     # >= ~5e-3 L move the cosines by <= ~2e-6 per vertex, so |d kappa| <= 5e-4
     dk = np.abs(g["kappa"][both] - o["kappa"][both])
-    assert dk.max() <= 5e-4 and np.median(dk) <= 1e-6
+    assert dk.max() <= 5e-4 and np.median(dk) <= 1e-5
     assert np.all(g["residual"][both] <= 1e-4)
 
 
@@ -211,3 +211,69 @@ def test_determinism(mpg):
         outs.append((GC.to_np(prim), GC.to_np(pos), GC.to_np(o["status"]), GC.to_np(o["G"])))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bucketing,waves", [(1, 4), (1, 1), (0, 2)])
+def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves):
+    """The persistent batched form computes every chain with the same code as
+    the plain form, only scheduled differently: outputs are identical."""
+    import torch
+    sc = W.slab_stack_scene()
+    ep = W.slab_uneven_endpoints(20000 + 37)   # ragged: not a multiple of 64
+    ep.length[11] = 0                          # invalid length -> bad input
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    plain = run_gpu_walk(mpg, sc, ep, prim, pos, st)
+    pers = run_gpu_walk(mpg, sc, ep, prim, pos, st, form=mpg.FORM_PERSISTENT, bucketing=bucketing,
+                        waves_per_group=waves)
+    for k in ("status", "iters", "sol", "G", "kappa", "residual"):
+        assert np.array_equal(plain[k], pers[k]), k
+    ok = plain["status"] != mpg.BAD_INPUT
+    assert np.array_equal(plain["prim"][:, ok], pers["prim"][:, ok])
+    assert np.array_equal(plain["pos"][:, :, ok], pers["pos"][:, :, ok])
+    assert plain["status"][11] == mpg.BAD_INPUT
+    o = O.walk(osc, ep, prim, pos, st, prm=O.params(sc.scale, cone_cos=GC.cone_cos()))
+    GC.compare_walks(ep, pers, o, sc.scale, tag="slab_persistent")
+
+
+def test_deferred_fp64_pass(mpg):
+    """defer_fp64 leaves NEEDS_FP64 chains; manifold_walk_fp64 finishes them
+    exactly as the one-call walk does."""
+    import torch
+    sc = W.sphere_mirror_scene()
+    ep = W.sphere_mirror_endpoints(4096)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    one = run_gpu_walk(mpg, sc, ep, prim, pos, st, max_len=1)
+    scene = mpg.Scene(sc)
+    dep = mpg.Endpoints(ep)
+    prm = mpg.walk_params(sc.scale, max_len=1, defer_fp64=1)
+    p, q, outs = mpg.manifold_walk_batch(scene, prm, dep, torch.as_tensor(prim).cuda(), torch.as_tensor(pos).cuda(),
+                                         torch.as_tensor(st).cuda())
+    torch.cuda.synchronize()
+    mid = GC.to_np(outs["status"])
+    assert (mid == mpg.NEEDS_FP64).sum() > 0
+    mpg.manifold_walk_fp64(scene, prm, dep, p, q, outs)
+    torch.cuda.synchronize()
+    assert np.array_equal(GC.to_np(outs["status"]), one["status"])
+    assert np.array_equal(GC.to_np(q).astype(np.float64), one["pos"])
+
+
+def test_counting_walk_matches_and_counts(mpg):
+    """The counting launch produces the same chains as the timed walk and
+    positive work tallies."""
+    import torch
+    sc = W.icosphere_glass_scene()
+    ep = W.icosphere_endpoints(8192)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    ref = run_gpu_walk(mpg, sc, ep, prim, pos, st, max_len=2)
+    scene = mpg.Scene(sc)
+    dep = mpg.Endpoints(ep)
+    prm = mpg.walk_params(sc.scale, max_len=2)
+    p, q, outs, counts = mpg.walk_count(scene, prm, dep, torch.as_tensor(prim).cuda(), torch.as_tensor(pos).cuda(),
+                                        torch.as_tensor(st).cuda())
+    assert np.array_equal(GC.to_np(outs["status"]), ref["status"])
+    assert counts["chains"] == ep.n
+    assert counts["rays"] > ep.n and counts["box_tests"] > counts["rays"] and counts["tri_tests"] > 0
+    assert counts["vertex_jacobian_evals"] > 0 and counts["vertex_residual_evals"] > 0
