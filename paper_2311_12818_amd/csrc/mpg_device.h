@@ -18,7 +18,8 @@ constexpr int KMAX = 8;
 constexpr int PRIM_NONE = (int)0x80000000;
 enum : int { ST_CONVERGED = 0, ST_MAX_ITER = 1, ST_SINGULAR = 2, ST_SIDE_INVALID = 3, ST_OCCLUDED = 4,
              ST_SEED_INVALID = 5, ST_FP64_REJECT = 6, ST_BAD_INPUT = 7,
-             ST_NEEDS_FP64 = 8 /* internal: converged, awaiting the FP64 pass */ };
+             ST_NEEDS_FP64 = 8 /* converged, awaiting the FP64 pass */,
+             ST_PENDING = 9 /* internal: converged in the walk kernel, awaiting the finish pass */ };
 enum : int { MAT_MIRROR = 0, MAT_DIELECTRIC = 1 };
 constexpr int P0_DIRECTION = -2;
 
@@ -192,8 +193,9 @@ __device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k ==
 // Returns false only on stack overflow (the library sizes stacks so that it
 // cannot happen).  h.prim == PRIM_NONE when nothing was hit.
 template <class STK>
-__device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& h, STK& stk) {
-  h.t = INFINITY;
+__device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& h, STK& stk,
+                      float tmax = INFINITY) {
+  h.t = tmax;
   h.prim = PRIM_NONE;
   stk.ray();
   for (int s = 0; s < S.n_spheres; ++s) {
@@ -572,13 +574,20 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
   for (int i = 0; i < N; ++i) {
     f3 o = i == 0 ? xD : xn[i > 0 ? i - 1 : 0];
     int excl = i == 0 ? PRIM_NONE : pn[i > 0 ? i - 1 : 0];
-    f3 tg = fmav(dl[i], beta, x[i]);
+    f3 step = dl[i] * beta;
+    f3 tg = x[i] + step;
     f3 d = tg - o;
     float l2 = dot(d, d);
     if (!(l2 > 0.0f)) return false;
-    d = d * rsq(l2);
+    float il = rsq(l2);
+    d = d * il;
+    // The surface is expected near the target: search [tmin, bound] first;
+    // the closest hit there is the closest overall.  Only a miss needs the
+    // unbounded traversal.
+    float bound = 1.5f * l2 * il + 2.0f * norm(step) + 4.0f * tmin;
     Hit h;
-    if (!trace(S, o, d, excl, tmin, h, stk)) return false;
+    if (!trace(S, o, d, excl, tmin, h, stk, bound)) return false;
+    if (h.prim == PRIM_NONE && !trace(S, o, d, excl, tmin, h, stk)) return false;
     if (h.prim == PRIM_NONE || prim_obj(S, h.prim) != obj[i]) return false;
     xn[i] = fmav(d, h.t, o);
     pn[i] = h.prim;
@@ -595,7 +604,7 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
 // was within tol_vertex L ends the walk as ST_NEEDS_FP64 (precision floor);
 // any other rejection sets beta = length / 2.
 template <int N, class STK>
-__device__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type, int* prim, f3* x,
+__device__ __forceinline__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type, int* prim, f3* x,
                          int& iters, STK& stk) {
   int obj[N];
 #pragma unroll
@@ -662,7 +671,7 @@ __device__ __forceinline__ float fresnel(float cos_i, float eta_i, float eta_t) 
 // current primitives (planar for triangles, radial projection for spheres).
 // On success xd holds the FP64 vertices and W their FP64 Jacobian sweep.
 template <int N, class STK>
-__device__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int type, const int* prim, d3* xd,
+__device__ __forceinline__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int type, const int* prim, d3* xd,
                            Sweep<double, N>& W, float& resid, STK& stk) {
   for (int k = 0; k < 2; ++k) {
     sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk);
@@ -714,7 +723,7 @@ __device__ __forceinline__ double fresnel_t(double cos_i, double eta_i, double e
 }
 
 template <typename T, int N, class STK>
-__device__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, vec3<T> nD, vec3<T> xL, int type,
+__device__ __forceinline__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, vec3<T> nD, vec3<T> xL, int type,
                             const int* prim, const vec3<T>* x, const Sweep<T, N>& W, STK& stk, WalkOut& R) {
   T kappa = 1;
 #pragma unroll
@@ -737,8 +746,9 @@ __device__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, 
     f3 d = xl - xn;
     float dist = norm(d);
     Hit h;
-    trace(S, xn, d * (1.0f / dist), prim[N - 1], P.tmin, h, stk);
-    if (h.prim != PRIM_NONE && h.t < dist * (1.0f - 1e-6f)) { R.status = ST_OCCLUDED; return; }
+    // only occluders strictly before the light matter
+    trace(S, xn, d * (1.0f / dist), prim[N - 1], P.tmin, h, stk, dist * (1.0f - 1e-6f));
+    if (h.prim != PRIM_NONE) { R.status = ST_OCCLUDED; return; }
   }
   vec3<T> wl = normalize(x[N - 1] - xL), t1, t2;
   onb(wl, t1, t2);
@@ -774,7 +784,7 @@ __device__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, 
 // grazing (where the FP32 Jacobian entries cancel) are left as ST_NEEDS_FP64
 // for the FP64 pass; the others are finished in FP32.
 template <int N, class STK>
-__device__ void finish(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
+__device__ __forceinline__ void finish(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
                        const f3* x, STK& stk, WalkOut& R) {
   Sweep<float, N> W;
   sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
@@ -786,7 +796,7 @@ __device__ void finish(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 
 // FP64 pass for one flagged chain: FP64 residual check and polish, then the
 // side / visibility tests, kappa and G in FP64.
 template <int N, class STK>
-__device__ void finish_fp64(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
+__device__ __forceinline__ void finish_fp64(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
                             f3* x, STK& stk, WalkOut& R) {
   d3 xd[N];
 #pragma unroll
@@ -818,7 +828,7 @@ __device__ __forceinline__ int guide_cell(const DevGuide& G, f3 x) {
   return (idx[2] * G.res + idx[1]) * G.res + idx[0];
 }
 
-__device__ bool p0_point(const DevScene& S, const WalkParams& P, int obj1, f3 xD, f3 nD, float u1, float u2,
+__device__ __forceinline__ bool p0_point(const DevScene& S, const WalkParams& P, int obj1, f3 xD, f3 nD, float u1, float u2,
                          float u3, f3& pt) {
   if (obj1 == P0_DIRECTION) {
     f3 ax = normalize(nD), b1, b2;
@@ -872,7 +882,7 @@ __device__ bool p0_point(const DevScene& S, const WalkParams& P, int obj1, f3 xD
 }
 
 template <class STK>
-__device__ bool guided_point(const DevScene& S, const DevGuide& G, int cell, uint64_t seed, uint64_t chain,
+__device__ __forceinline__ bool guided_point(const DevScene& S, const DevGuide& G, int cell, uint64_t seed, uint64_t chain,
                              uint64_t trial, const U8& U0, STK& stk, f3& pt) {
   const int K = G.comps;
   for (int attempt = 0; attempt <= 8; ++attempt) {
@@ -904,7 +914,7 @@ __device__ bool guided_point(const DevScene& S, const DevGuide& G, int cell, uin
 
 // One seed chain of length N.  Returns 0 or ST_SEED_INVALID.
 template <int N, class STK>
-__device__ int sample_seed(const DevScene& S, const DevGuide* G, const WalkParams& P, int type, int obj1, f3 xD,
+__device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G, const WalkParams& P, int type, int obj1, f3 xD,
                            f3 nD, uint64_t seed, uint64_t chain, uint64_t trial, float alpha, int* prim, f3* pos,
                            STK& stk) {
   U8 U = philox_uniforms(seed, chain, trial, 0);

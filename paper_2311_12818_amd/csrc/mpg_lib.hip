@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -328,7 +329,7 @@ __device__ __forceinline__ Stack lane_stack(int depth) {
 }
 
 template <int N, class STK>
-__device__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
+__device__ __forceinline__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
                          uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
                          STK& stk) {
   int prim[N];
@@ -384,7 +385,7 @@ struct WalkIO {
 };
 
 template <int N, class STK>
-__device__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+__device__ __forceinline__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
                          STK& stk) {
   const size_t NN = E.N;
   int prim[N];
@@ -419,8 +420,9 @@ __device__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E
     int it = 0;
     R.status = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
     R.iters = it;
-    if (R.status == ST_CONVERGED) finish<N>(S, P, xD, nD, xL, type, prim, x, stk, R);
-    // ST_NEEDS_FP64 chains are finished by the FP64 pass
+    // converged chains are finished by the finish pass (FP32) and, when
+    // flagged there or stalled here, by the FP64 pass
+    if (R.status == ST_CONVERGED) R.status = ST_PENDING;
   }
   io.status[c] = (int8_t)R.status;
   if (io.iters) io.iters[c] = (uint8_t)R.iters;
@@ -474,9 +476,59 @@ __global__ void __launch_bounds__(256) k_walk_plain(DevScene S, WalkParams P, Ep
   walk_dispatch<NMAX>(S, P, E, io, c, stk);
 }
 
+// Finish pass over the chains the walk left as ST_PENDING (FP32 side and
+// visibility tests, kappa, G; near-singular or grazing chains become
+// ST_NEEDS_FP64).
+template <int N, class STK>
+__device__ __forceinline__ void finish_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+                           STK& stk) {
+  const size_t NN = E.N;
+  int prim[N];
+  f3 x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim[i] = io.prim_out[i * NN + c];
+    x[i] = {io.pos_out[(0 * KMAX + i) * NN + c], io.pos_out[(1 * KMAX + i) * NN + c],
+            io.pos_out[(2 * KMAX + i) * NN + c]};
+  }
+  WalkOut R;
+  R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
+  finish<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
+  io.status[c] = (int8_t)R.status;
+  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
+  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
+  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
+  if (io.resid) io.resid[c] = R.resid;
+}
+
+template <int NMAX, class STK>
+__device__ __forceinline__ void finish_dispatch(const DevScene& S, const WalkParams& P, const EpView& E,
+                                                const WalkIO& io, int c, STK& stk) {
+  if (io.status[c] != ST_PENDING) return;
+  int n = E.len[c];
+  switch (n) {
+    case 1: finish_one<1>(S, P, E, io, c, stk); break;
+    case 2: if (NMAX >= 2) finish_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
+    case 3: if (NMAX >= 3) finish_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
+    case 4: if (NMAX >= 4) finish_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
+    case 5: if (NMAX >= 5) finish_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
+    case 6: if (NMAX >= 6) finish_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
+    case 7: if (NMAX >= 7) finish_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
+    default: if (NMAX >= 8) finish_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
+  }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_finish_pass(DevScene S, WalkParams P, EpView E, WalkIO io) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  finish_dispatch<NMAX>(S, P, E, io, c, stk);
+}
+
 // FP64 pass over the chains the walk left as ST_NEEDS_FP64.
 template <int N, class STK>
-__device__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+__device__ __forceinline__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
                          STK& stk) {
   const size_t NN = E.N;
   int prim[N];
@@ -534,6 +586,7 @@ __global__ void __launch_bounds__(256) k_walk_count(DevScene S, WalkParams P, Ep
   Stack base = lane_stack(P.depth);
   CountStack stk{base.base, base.depth, 0, 0, 0, 0, 0, 0, 0};
   if (c < E.N) walk_dispatch<NMAX>(S, P, E, io, c, stk);
+  if (c < E.N) finish_dispatch<NMAX>(S, P, E, io, c, stk);
   if (c < E.N && io.status[c] == ST_NEEDS_FP64) {
     int n = E.len[c];
     switch (n) {
@@ -590,6 +643,18 @@ static walk_kernel_t plain_kernel(int nmax) {
     default: return k_walk_plain<8>;
   }
 }
+static walk_kernel_t finish_kernel(int nmax) {
+  switch (nmax) {
+    case 1: return k_finish_pass<1>;
+    case 2: return k_finish_pass<2>;
+    case 3: return k_finish_pass<3>;
+    case 4: return k_finish_pass<4>;
+    case 5: return k_finish_pass<5>;
+    case 6: return k_finish_pass<6>;
+    case 7: return k_finish_pass<7>;
+    default: return k_finish_pass<8>;
+  }
+}
 static walk_kernel_t fp64_kernel(int nmax) {
   switch (nmax) {
     case 1: return k_fp64_pass<1>;
@@ -619,7 +684,7 @@ struct InvIO {
 };
 
 template <int N, class STK>
-__device__ void inv_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E,
+__device__ __forceinline__ void inv_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E,
                         const InvIO& io, int c, STK& stk) {
   const size_t NN = E.N;
   f3 tx[N];
@@ -783,6 +848,8 @@ extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_par
     if (st2 != MPG_OK) return st2;
   } else if (p->form == MPG_FORM_PLAIN) {
     hipLaunchKernelGGL(plain_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(finish_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);
     HIP_TRY(hipGetLastError());
   } else {
     return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: unknown form");
