@@ -273,6 +273,14 @@ mpg_status estimate_inv_prob(const mpg_scene* scene, const mpg_guide* guide, con
 mpg_status fit_guide(const mpg_scene* scene, const float* d_samples, int32_t n_samples, mpg_guide* guide,
                      mpg_workspace* ws, void* hip_stream);
 
+/* Packs walked chains into fit_guide's 32-byte sample records: {x_D, x and y
+ * of x_1, w, 0, 0} with the sample weight w = T <1/P> (Eq. eq_weight),
+ * T = kappa G (L_o = 1) and <1/P> = d_inv_prob; w = 0 unless d_status is
+ * MPG_CONVERGED.  d_samples is [N][8] float. */
+mpg_status make_guide_samples(const mpg_endpoints* ep, const mpg_chains* chains, const int8_t* d_status,
+                              const float* d_G, const float* d_kappa, const float* d_inv_prob, float* d_samples,
+                              void* hip_stream);
+
 /* Adjoint of converged chains by the implicit function theorem (Sec. 5.2):
  * given cotangents of the vertex positions (d_grad_pos [3][K][N], nullable)
  * and of G (d_grad_G [N], nullable), accumulates the gradients with respect

@@ -797,12 +797,16 @@ struct Guide {
   std::vector<double> chol;    // [cells][comps][3]  L00, L10, L11
 };
 
+// Cell of x_D.  The cell is an integer decided by floating point, so it is
+// taken in the precision of the GPU kernel (FP32, same operation order) to
+// make the two sides agree exactly.
 static int guide_cell(const Guide& g, const V3d& x) {
   int idx[3];
   for (int a = 0; a < 3; ++a) {
-    double f = (x[a] - g.lo[a]) / (g.hi[a] - g.lo[a]) * g.res;
-    int k = (int)std::floor(f);
+    float lo = (float)g.lo[a], hi = (float)g.hi[a];
+    float f = ((float)x[a] - lo) / (hi - lo) * (float)g.res;
     if (!(f == f)) return -1;
+    int k = (int)std::floor(f);
     idx[a] = std::min(std::max(k, 0), g.res - 1);
   }
   return (idx[2] * g.res + idx[1]) * g.res + idx[0];
@@ -989,7 +993,7 @@ static void em_cell(const EMParams& ep, const std::vector<int>& idx, const float
   }
   sxx = sxx / Wt + ep.reg; sxy /= Wt; syy = syy / Wt + ep.reg;
   for (int j = 0; j < K; ++j) {
-    int s = (int)std::floor((j + 0.5) * m / K);
+    int s = (2 * j + 1) * m / (2 * K);  // floor((j + 1/2) m / K)
     pi[j] = 1.0 / K;
     mu[2 * j] = X[2 * s];
     mu[2 * j + 1] = X[2 * s + 1];
@@ -1037,10 +1041,12 @@ static void em_cell(const EMParams& ep, const std::vector<int>& idx, const float
   *valid = 1;
 }
 
+// Cell of a training sample, decided in FP32 like the GPU kernel (see guide_cell).
 static int em_cell_index(const EMParams& ep, const float* r) {
   int idx[3];
   for (int a = 0; a < 3; ++a) {
-    double f = ((double)r[a] - ep.lo[a]) / (ep.hi[a] - ep.lo[a]) * ep.res;
+    float lo = (float)ep.lo[a], hi = (float)ep.hi[a];
+    float f = (r[a] - lo) / (hi - lo) * (float)ep.res;
     if (!(f == f)) return -1;
     int k = (int)std::floor(f);
     idx[a] = std::min(std::max(k, 0), ep.res - 1);
@@ -1374,7 +1380,7 @@ void orc_fit_guide(int n_samples, const float* samples, int res, int comps, int 
   std::vector<std::vector<int>> members(cells);
   for (int i = 0; i < n_samples; ++i) {
     const float* r = samples + 8 * (size_t)i;
-    if (!(r[5] > 0.0f)) continue;
+    if (!(r[5] > 0.0f) || !std::isfinite(r[3]) || !std::isfinite(r[4]) || !std::isfinite(r[5])) continue;
     int cidx = em_cell_index(ep, r);
     if (cidx >= 0) members[cidx].push_back(i);
   }

@@ -102,6 +102,7 @@ def lib():
         L.estimate_inv_prob.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                         C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, F32, P, P, P, P, P]
         L.fit_guide.argtypes = [P, P, I32, P, P, P]
+        L.make_guide_samples.argtypes = [C.POINTER(mpg_endpoints), C.POINTER(mpg_chains), P, P, P, P, P, P]
         L.manifold_walk_fp64.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                          C.POINTER(mpg_chains), C.POINTER(mpg_walk_out), P]
         L.mpg_walk_count.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.POINTER(mpg_chains),
@@ -111,7 +112,7 @@ def lib():
         for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
                      "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
-                     "manifold_walk_fp64", "mpg_walk_count"]:
+                     "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples"]:
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -358,10 +359,21 @@ def estimate_inv_prob(scene: Scene, params: mpg_walk_params, ep: Endpoints, tpri
     return trials, inv, trunc
 
 
+def make_guide_samples(ep: Endpoints, pos, outs, inv_prob):
+    """Sample records [N, 8] (x_D, x, y of x_1, w = kappa G <1/P>, 0, 0) on the device."""
+    torch = _torch()
+    out = torch.empty((ep.N, 8), dtype=torch.float32, device=ep.xD.device)
+    ch = mpg_chains(0, pos.data_ptr())
+    _check(lib().make_guide_samples(C.byref(ep.c()), C.byref(ch), outs["status"].data_ptr(), outs["G"].data_ptr(),
+                                    outs["kappa"].data_ptr(), inv_prob.data_ptr(), out.data_ptr(), _stream()),
+           "make_guide_samples")
+    return out
+
+
 def fit_guide(scene: Scene, samples, guide: Guide, ws: Workspace):
     """samples: float32 device tensor [M, 8] (x_D, u, v, w, 0, 0)."""
-    _check(lib().fit_guide(scene.h, samples.data_ptr(), int(samples.shape[0]), guide.h, ws.h, _stream()),
-           "fit_guide")
+    _check(lib().fit_guide(scene.h if scene is not None else None, samples.data_ptr(), int(samples.shape[0]),
+                           guide.h, ws.h, _stream()), "fit_guide")
     return guide
 
 

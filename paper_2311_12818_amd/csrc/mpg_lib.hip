@@ -60,6 +60,7 @@ struct mpg_guide {
   float* cov = nullptr;
   float* chol = nullptr;
   int32_t* count = nullptr;
+  int32_t* scratch = nullptr;  // fit_guide per-cell offsets and cursors
   std::vector<void*> allocs;
   DevGuide dev() const {
     DevGuide g;
