@@ -283,10 +283,20 @@ mpg_status make_guide_samples(const mpg_endpoints* ep, const mpg_chains* chains,
 
 /* Adjoint of converged chains by the implicit function theorem (Sec. 5.2):
  * given cotangents of the vertex positions (d_grad_pos [3][K][N], nullable)
- * and of G (d_grad_G [N], nullable), accumulates the gradients with respect
- * to x_D (d_grad_xD [3][N]), x_L (d_grad_xL [3][N]) and the height-field
- * parameters (d_grad_theta [P], P = 2 * sum of n_sines, added atomically).
- * Chains whose status is not MPG_CONVERGED contribute nothing. */
+ * and of G (d_grad_G [N], nullable) for the loss
+ *   l = sum_chains (sum_i grad_pos_i . x_i + grad_G G),
+ * writes the per-chain gradients with respect to x_D (d_grad_xD [3][N]) and
+ * x_L (d_grad_xL [3][N]), and ADDS the gradient with respect to the
+ * height-field parameters (d_grad_theta [P], P = 2 * sum of n_sines, in
+ * scene order: amplitude, phase per sine; the caller zeroes it first; atomic
+ * float additions, so the summation order is not deterministic; may be NULL
+ * when P = 0).  The surface parameters move triangle vertices and vertex
+ * normals; a chain vertex rides on its triangle at fixed barycentric
+ * coordinates.  Chains whose status is not MPG_CONVERGED (or whose primitive
+ * ids are out of range) get zero gradients and add nothing.  The chains must
+ * be the converged output of manifold_walk_batch on the same scene and
+ * endpoints; params->max_len bounds the lengths handled.  All buffers are
+ * device memory owned by the caller; the call is asynchronous on hip_stream. */
 mpg_status manifold_walk_adjoint(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
                                  const mpg_chains* converged, const int8_t* d_status, const float* d_grad_pos,
                                  const float* d_grad_G, float* d_grad_xD, float* d_grad_xL, float* d_grad_theta,

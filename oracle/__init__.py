@@ -70,6 +70,10 @@ def _declare(L):
                            P, P, P, P, C.c_int]
     L.orc_inv_prob.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, C.c_int,
                                C.c_int, U64, D, P, P, P, C.c_int]
+    L.orc_scene_set_theta.restype = C.c_int
+    L.orc_scene_set_theta.argtypes = [P, C.c_int, P]
+    L.orc_adjoint.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
+                              C.c_int]
     L.orc_fit_guide.argtypes = [C.c_int, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, D, P, P, P, P, P, C.c_int]
 
 
@@ -105,6 +109,17 @@ class Scene:
                                         hf.y1, hf.z0, len(hf.amp), *[_p(a) for a in arr])
         self.scale = float(sc.scale)
         self.src = sc
+
+    def n_theta(self):
+        return sum(2 * len(hf.amp) for hf in self.src.heightfields)
+
+    def set_theta(self, theta):
+        """Replace the height-field parameters (amplitude, phase per sine, in
+        height-field order): vertices and normals are recomputed in FP64 and
+        the BVH is rebuilt."""
+        th = _c(theta, np.float64)
+        if lib().orc_scene_set_theta(self.h, th.shape[0], _p(th)) != 0:
+            raise ValueError("theta has the wrong length")
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -258,3 +273,27 @@ def fit_guide(samples, lo, hi, res=32, comps=8, iters=30, min_samples=16, reg=No
     lib().orc_fit_guide(M, _p(s), res, comps, iters, min_samples, _p(_c(lo, np.float64)), _p(_c(hi, np.float64)),
                         float(reg), _p(valid), _p(pi), _p(mu), _p(cov), _p(count), nthreads)
     return Guide(lo, hi, res, comps, target_obj, valid, pi, mu, cov, count)
+
+
+def adjoint(osc: Scene, ep, prim, pos, status, grad_pos, grad_G, theta=None, prm=None, nthreads=0):
+    """Per-chain gradients of l = sum_i grad_pos_i . x_i + grad_G * G over
+    converged chains (forward implicit-function-theorem form in FP64).
+
+    Returns (grad_xD [3, N], grad_xL [3, N], grad_theta [N, P], ok [N])."""
+    N = ep.n
+    prm = prm or params(osc.scale)
+    P = osc.n_theta()
+    th = _c(np.zeros(0) if theta is None else theta, np.float64)
+    if theta is None and P:
+        th = _c([v for hf in osc.src.heightfields for ap in zip(hf.amp, hf.phase) for v in ap], np.float64)
+    gxD = np.zeros((3, N))
+    gxL = np.zeros((3, N))
+    gth = np.zeros((N, max(P, 1)))
+    ok = np.zeros(N, np.int8)
+    gp = None if grad_pos is None else _c(grad_pos, np.float64)
+    gg = None if grad_G is None else _c(grad_G, np.float64)
+    lib().orc_adjoint(osc.h, C.byref(prm), N, _p(_c(ep.xD, np.float64)), _p(_c(ep.nD, np.float64)),
+                      _p(_c(ep.xL, np.float64)), _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)),
+                      _p(_c(prim, np.int32)), _p(_c(pos, np.float64)), _p(_c(status, np.int8)), _p(gp), _p(gg),
+                      _p(th), _p(gxD), _p(gxL), _p(gth), _p(ok), nthreads)
+    return gxD, gxL, gth[:, :P], ok

@@ -1055,6 +1055,259 @@ static int em_cell_index(const EMParams& ep, const float* r) {
 }
 
 // ---------------------------------------------------------------------------
+// Gradients of converged chains (continuity of the specular manifold by the
+// implicit function theorem, Sec. 5.2), forward form in FP64:
+//   C(y*, p) = 0  =>  dy/dp = -J^-1 dC/dp,
+//   dx_i/dp = dx_i/dp|_y + dx_i/dy dy/dp,   dG/dp = dG/dp|_y + dG/dy dy/dp,
+// for p = (x_D, x_L, theta).  Triangles use a barycentric chart whose
+// vertices (and normals) follow the height-field parameters theta; spheres
+// use the tangent chart of the walk.  G needs J (first derivatives of C), so
+// everything is evaluated with nested dual numbers: the inner duals carry
+// d/dy and d/du_L (J and B), the outer duals d/d(y, x_D, x_L, theta).
+// ---------------------------------------------------------------------------
+static const int ADJ_P = 32;                       // height-field parameters supported
+static const int ADJ_OUT = 2 * KMAX + 6 + ADJ_P;   // outer directions
+static const int ADJ_IN = 2 * KMAX + 2;            // inner directions
+typedef Dual<double, ADJ_OUT> DA;
+typedef Dual<DA, ADJ_IN> DB;
+
+struct AdjVertex {
+  int prim = 0;
+  bool sphere = false;
+  int hf = -1;                  // height field of the triangle, or -1
+  double b1 = 0, b2 = 0;        // base barycentrics (triangles)
+  V3d base;                     // base position (spheres)
+  V3d e1, e2;                   // tangent frame (spheres)
+  VGeo geo;                     // walk geometry at the base (etas, material)
+};
+
+static int hf_of_vertex(const Scene& s, int v) {
+  for (size_t h = 0; h < s.hfs.size(); ++h)
+    if (v >= s.hfs[h].first_vert && v < s.hfs[h].first_vert + s.hfs[h].res * s.hfs[h].res) return (int)h;
+  return -1;
+}
+
+static int hf_param_base(const Scene& s, int h) {
+  int b = 0;
+  for (int k = 0; k < h; ++k) b += 2 * s.hfs[k].n_sines;
+  return b;
+}
+
+// Vertex v of the mesh as a function of theta: height-field vertices are
+// recomputed from the sine sum at their (x, y); others are the stored data.
+template <class T>
+static void mesh_vertex(const Scene& s, int v, const T* theta, V3<T>* P, V3<T>* N) {
+  int h = hf_of_vertex(s, v);
+  if (h < 0) {
+    *P = lift<T>(s.P[v]);
+    *N = lift<T>(s.N[v]);
+    return;
+  }
+  const HeightField& H = s.hfs[h];
+  int base = hf_param_base(s, h);
+  double x = s.P[v].x, y = s.P[v].y;
+  T z = T(H.z0), hx = T(0), hy = T(0);
+  for (int k = 0; k < H.n_sines; ++k) {
+    T amp = theta[base + 2 * k], ph = theta[base + 2 * k + 1];
+    T arg = T(H.freq[k] * (std::cos(H.psi[k]) * x + std::sin(H.psi[k]) * y)) + ph;
+    z = z + amp * sin(arg);
+    T c = amp * T(H.freq[k]) * cos(arg);
+    hx = hx + c * T(std::cos(H.psi[k]));
+    hy = hy + c * T(std::sin(H.psi[k]));
+  }
+  *P = V3<T>(T(x), T(y), z);
+  *N = normalize(V3<T>(-hx, -hy, T(1)));
+}
+
+struct AdjChain {
+  int n = 0, type = 0;
+  AdjVertex v[KMAX];
+  double ea[KMAX], eb[KMAX];
+};
+
+// Positions and shading normals at chart coordinates y (2n) and theta.
+template <class T>
+static void adj_geometry(const Scene& s, const AdjChain& c, const T* y, const T* theta, V3<T>* x, V3<T>* ns,
+                         V3<T>* e1) {
+  for (int i = 0; i < c.n; ++i) {
+    const AdjVertex& a = c.v[i];
+    if (a.sphere) {
+      int k = -1 - a.prim;
+      V3<T> cen = lift<T>(s.sc[k]);
+      V3<T> d = lift<T>(a.base - s.sc[k]) + lift<T>(a.e1) * y[2 * i] + lift<T>(a.e2) * y[2 * i + 1];
+      V3<T> n = normalize(d);
+      x[i] = cen + n * T(s.sr[k]);
+      ns[i] = n;
+      e1[i] = lift<T>(a.e1);
+      continue;
+    }
+    V3<T> P[3], N[3];
+    for (int k = 0; k < 3; ++k) mesh_vertex(s, s.tri[3 * a.prim + k], theta, &P[k], &N[k]);
+    T b1 = T(a.b1) + y[2 * i], b2 = T(a.b2) + y[2 * i + 1], b0 = T(1) - b1 - b2;
+    x[i] = P[0] * b0 + P[1] * b1 + P[2] * b2;
+    ns[i] = normalize(N[0] * b0 + N[1] * b1 + N[2] * b2);
+    e1[i] = normalize(P[1] - P[0]);
+  }
+}
+
+// C and G at chart coordinates y, endpoints, theta (T = DA gives outer
+// derivatives of both).
+static void adj_eval(const Scene& s, const AdjChain& c, const DA* yA, const V3<DA>& xD, const V3<DA>& xL,
+                     const DA* thA, const V3d& nD, DA* C, DA* G, V3<DA>* xout) {
+  const int n = c.n, m = 2 * n;
+  DB y[2 * KMAX], th[ADJ_P];
+  for (int k = 0; k < m; ++k) y[k] = DB::var(yA[k], k);
+  for (int k = 0; k < ADJ_P; ++k) th[k] = DB(thA[k], 0);
+  V3d wl0;  // x_L tangent plane perpendicular to x_n - x_L (from the base values)
+  V3<DB> x[KMAX + 2], ns[KMAX], e1[KMAX];
+  {
+    V3<DB> xx[KMAX], nn[KMAX], ee[KMAX];
+    adj_geometry(s, c, y, th, xx, nn, ee);
+    for (int i = 0; i < n; ++i) { x[i + 1] = xx[i]; ns[i] = nn[i]; e1[i] = ee[i]; }
+  }
+  V3d xn_val(val(x[n].x), val(x[n].y), val(x[n].z));
+  V3d xL_val(val(xL.x), val(xL.y), val(xL.z));
+  wl0 = normalize(xn_val - xL_val);
+  V3d t1, t2;
+  onb(wl0, &t1, &t2);
+  DB u1 = DB::var(DA(0.0), ADJ_IN - 2), u2 = DB::var(DA(0.0), ADJ_IN - 1);
+  x[0] = V3<DB>(DB(xD.x, 0), DB(xD.y, 0), DB(xD.z, 0));
+  x[n + 1] = V3<DB>(DB(xL.x, 0), DB(xL.y, 0), DB(xL.z, 0)) + lift<DB>(t1) * u1 + lift<DB>(t2) * u2;
+  DB Cb[2 * KMAX];
+  for (int i = 0; i < n; ++i) {
+    V3<DB> wi = normalize(x[i] - x[i + 1]), wo = normalize(x[i + 2] - x[i + 1]);
+    V3<DB> h = normalize(wi * DB(c.ea[i]) + wo * DB(c.eb[i]));
+    V3<DB> sv = normalize(e1[i] - ns[i] * dot(e1[i], ns[i]));
+    V3<DB> tv = cross(ns[i], sv);
+    Cb[2 * i] = dot(h, sv);
+    Cb[2 * i + 1] = dot(h, tv);
+  }
+  // J (m x m) and B (m x 2) as DA; solve J X = -B in DA arithmetic
+  DA J[4 * KMAX * KMAX], X[4 * KMAX];
+  for (int r = 0; r < m; ++r) {
+    C[r] = Cb[r].v;
+    for (int k = 0; k < m; ++k) J[r * m + k] = Cb[r].d[k];
+    X[2 * r] = -Cb[r].d[ADJ_IN - 2];
+    X[2 * r + 1] = -Cb[r].d[ADJ_IN - 1];
+  }
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(val(J[r * m + col])) > std::fabs(val(J[piv * m + col]))) piv = r;
+    if (piv != col) {
+      for (int k = 0; k < m; ++k) std::swap(J[piv * m + k], J[col * m + k]);
+      std::swap(X[2 * piv], X[2 * col]);
+      std::swap(X[2 * piv + 1], X[2 * col + 1]);
+    }
+    for (int r = col + 1; r < m; ++r) {
+      DA f = J[r * m + col] / J[col * m + col];
+      for (int k = col; k < m; ++k) J[r * m + k] = J[r * m + k] - f * J[col * m + k];
+      X[2 * r] = X[2 * r] - f * X[2 * col];
+      X[2 * r + 1] = X[2 * r + 1] - f * X[2 * col + 1];
+    }
+  }
+  for (int col = m - 1; col >= 0; --col)
+    for (int q = 0; q < 2; ++q) {
+      DA acc = X[2 * col + q];
+      for (int k = col + 1; k < m; ++k) acc = acc - J[col * m + k] * X[2 * k + q];
+      X[2 * col + q] = acc / J[col * m + col];
+    }
+  // d x_1 / d u = (d x_1 / d y_1) X_1; the position map's inner derivatives
+  V3<DA> dx[2];
+  for (int q = 0; q < 2; ++q) {
+    V3<DA> col0(x[1].x.d[0], x[1].y.d[0], x[1].z.d[0]);
+    V3<DA> col1(x[1].x.d[1], x[1].y.d[1], x[1].z.d[1]);
+    dx[q] = col0 * X[q] + col1 * X[2 + q];
+  }
+  V3<DA> x1(x[1].x.v, x[1].y.v, x[1].z.v);
+  V3<DA> dd = x1 - xD;
+  DA len = norm(dd);
+  V3<DA> w = dd * (DA(1.0) / len);
+  V3<DA> dw0 = (dx[0] - w * dot(w, dx[0])) * (DA(1.0) / len);
+  V3<DA> dw1 = (dx[1] - w * dot(w, dx[1])) * (DA(1.0) / len);
+  *G = fabs(dot(lift<DA>(nD), w)) * fabs(dot(w, cross(dw0, dw1)));
+  for (int i = 0; i < n; ++i) xout[i] = V3<DA>(x[i + 1].x.v, x[i + 1].y.v, x[i + 1].z.v);
+}
+
+// Loss gradient of one converged chain: l = sum_i r_i . x_i + g G.
+static bool chain_gradient(const Scene& s, const Params& p, int n, int type, const V3d& xD, const V3d& nD,
+                           const V3d& xL, const int* prim, const V3d* pos, const V3d* r, double g, const double* theta,
+                           double* gxD, double* gxL, double* gth) {
+  (void)p;
+  AdjChain c;
+  c.n = n;
+  c.type = type;
+  V3d xs[KMAX];
+  for (int i = 0; i < n; ++i) {
+    AdjVertex& a = c.v[i];
+    a.prim = prim[i];
+    a.geo = make_geo(s, prim[i], pos[i]);
+    xs[i] = pos[i];
+    if (prim[i] < 0) {
+      a.sphere = true;
+      a.base = pos[i];
+      a.e1 = a.geo.e1;
+      a.e2 = a.geo.e2;
+    } else {
+      V3d P0, P1, P2;
+      tri_verts(s, prim[i], &P0, &P1, &P2);
+      V3d E1 = P1 - P0, E2 = P2 - P0, q = pos[i] - P0;
+      double d11 = dot(E1, E1), d12 = dot(E1, E2), d22 = dot(E2, E2), q1 = dot(q, E1), q2 = dot(q, E2);
+      double den = d11 * d22 - d12 * d12;
+      a.b1 = (d22 * q1 - d12 * q2) / den;
+      a.b2 = (d11 * q2 - d12 * q1) / den;
+      a.hf = hf_of_vertex(s, s.tri[3 * prim[i]]);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    V3d xp = i == 0 ? xD : xs[i - 1];
+    etas(c.v[i].geo, (type >> i) & 1, normalize(xp - xs[i]), &c.ea[i], &c.eb[i]);
+  }
+  const int m = 2 * n;
+  const int oy = 0, oD = 2 * KMAX, oL = 2 * KMAX + 3, oT = 2 * KMAX + 6;
+  DA yA[2 * KMAX], thA[ADJ_P];
+  for (int k = 0; k < m; ++k) yA[k] = DA::var(0.0, oy + k);
+  int P = 0;
+  for (size_t h = 0; h < s.hfs.size(); ++h) P += 2 * s.hfs[h].n_sines;
+  if (P > ADJ_P) return false;
+  for (int k = 0; k < ADJ_P; ++k) thA[k] = k < P ? DA::var(theta[k], oT + k) : DA(0.0);
+  V3<DA> xDA(DA::var(xD.x, oD), DA::var(xD.y, oD + 1), DA::var(xD.z, oD + 2));
+  V3<DA> xLA(DA::var(xL.x, oL), DA::var(xL.y, oL + 1), DA::var(xL.z, oL + 2));
+  DA C[2 * KMAX], G;
+  V3<DA> x[KMAX];
+  adj_eval(s, c, yA, xDA, xLA, thA, nD, C, &G, x);
+  // dy/dp = -J^-1 dC/dp for every outer parameter direction
+  const int np = 6 + P;
+  std::vector<double> J(m * m), R((size_t)m * np);
+  for (int r = 0; r < m; ++r) {
+    for (int k = 0; k < m; ++k) J[r * m + k] = C[r].d[oy + k];
+    for (int q = 0; q < np; ++q) R[(size_t)r * np + q] = -C[r].d[q < 6 ? oD + q : oT + (q - 6)];
+  }
+  if (!dense_solve(m, J.data(), np, R.data())) return false;
+  for (int q = 0; q < np; ++q) {
+    int od = q < 6 ? oD + q : oT + (q - 6);
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double dxi[3];
+      for (int a = 0; a < 3; ++a) {
+        const DA& xa = x[i][a];
+        double v = xa.d[od];
+        for (int k = 0; k < m; ++k) v += xa.d[oy + k] * R[(size_t)k * np + q];
+        dxi[a] = v;
+      }
+      tot += r[i].x * dxi[0] + r[i].y * dxi[1] + r[i].z * dxi[2];
+    }
+    double dG = G.d[od];
+    for (int k = 0; k < m; ++k) dG += G.d[oy + k] * R[(size_t)k * np + q];
+    tot += g * dG;
+    if (q < 3) gxD[q] = tot;
+    else if (q < 6) gxL[q - 3] = tot;
+    else gth[q - 6] = tot;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // threads
 // ---------------------------------------------------------------------------
 template <class F>
@@ -1087,6 +1340,22 @@ using namespace oracle;
 // ---------------------------------------------------------------------------
 // C interface (ctypes)
 // ---------------------------------------------------------------------------
+static void build_bvh(Scene* s) {
+  int nt = s->ntri();
+  s->nodes.clear();
+  s->order.clear();
+  if (nt == 0) return;
+  std::vector<V3d> cen(nt);
+  for (int t = 0; t < nt; ++t) {
+    V3d a, b, c;
+    tri_verts(*s, t, &a, &b, &c);
+    cen[t] = (a + b + c) * (1.0 / 3.0);
+  }
+  s->order.resize(nt);
+  for (int t = 0; t < nt; ++t) s->order[t] = t;
+  build_node(*s, cen, 0, nt);
+}
+
 extern "C" {
 
 struct orc_params {
@@ -1115,17 +1384,7 @@ void* orc_scene_create(int nv, const float* verts, const float* normals, int nt,
     s->sobj.push_back(sphere_obj[k]);
   }
   s->scale = scale;
-  if (nt > 0) {
-    std::vector<V3d> cen(nt);
-    for (int t = 0; t < nt; ++t) {
-      V3d a, b, c;
-      tri_verts(*s, t, &a, &b, &c);
-      cen[t] = (a + b + c) * (1.0 / 3.0);
-    }
-    s->order.resize(nt);
-    for (int t = 0; t < nt; ++t) s->order[t] = t;
-    build_node(*s, cen, 0, nt);
-  }
+  build_bvh(s);
   // area CDFs per object and over all objects; xy bounds per object
   s->cdf.assign(nobj + 1, {});
   s->cdf_prim.assign(nobj + 1, {});
@@ -1388,6 +1647,65 @@ void orc_fit_guide(int n_samples, const float* samples, int res, int comps, int 
     count[c] = (int)members[c].size();
     em_cell(ep, members[c], samples, &valid[c], pi + (size_t)c * comps, mu + (size_t)c * comps * 2,
             cov + (size_t)c * comps * 3);
+  });
+}
+
+// Replace the height-field parameters theta [2 * sum n_sines] (amplitude,
+// phase per sine): vertex positions and normals of every height field are
+// recomputed from the sine sum in FP64 and the BVH is rebuilt.
+int orc_scene_set_theta(void* sp, int n, const double* theta) {
+  Scene* s = (Scene*)sp;
+  int P = 0;
+  for (const HeightField& h : s->hfs) P += 2 * h.n_sines;
+  if (n != P || P > ADJ_P) return -1;
+  for (size_t h = 0; h < s->hfs.size(); ++h) {
+    HeightField& H = s->hfs[h];
+    int base = hf_param_base(*s, (int)h);
+    for (int k = 0; k < H.n_sines; ++k) { H.amp[k] = theta[base + 2 * k]; H.phase[k] = theta[base + 2 * k + 1]; }
+    for (int v = H.first_vert; v < H.first_vert + H.res * H.res; ++v) {
+      V3d P, N;
+      mesh_vertex<double>(*s, v, theta, &P, &N);
+      s->P[v] = P;
+      s->N[v] = N;
+    }
+  }
+  build_bvh(s);
+  return 0;
+}
+
+// Per-chain loss gradients (FP64 forward IFT with nested duals).  theta is
+// the scene's current height-field parameters [P]; grad_theta is [N][P].
+void orc_adjoint(void* sp, const orc_params* pp, int N, const double* xD, const double* nD, const double* xL,
+                 const uint8_t* len, const uint8_t* type, const int32_t* prim, const double* pos, const int8_t* status,
+                 const double* grad_pos, const double* grad_G, const double* theta, double* grad_xD, double* grad_xL,
+                 double* grad_theta, int8_t* ok, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  Params p = to_params(pp);
+  int P = 0;
+  for (size_t h = 0; h < s.hfs.size(); ++h) P += 2 * s.hfs[h].n_sines;
+  parallel_for(N, nthreads, [&](int c) {
+    for (int a = 0; a < 3; ++a) { grad_xD[(size_t)a * N + c] = 0.0; grad_xL[(size_t)a * N + c] = 0.0; }
+    for (int k = 0; k < P; ++k) grad_theta[(size_t)c * P + k] = 0.0;
+    ok[c] = 0;
+    int n = len[c];
+    if (status[c] != ST_CONVERGED || n < 1 || n > KMAX) return;
+    int pr[KMAX];
+    V3d x[KMAX], r[KMAX];
+    for (int i = 0; i < n; ++i) {
+      pr[i] = prim[(size_t)i * N + c];
+      x[i] = V3d(pos[((size_t)0 * KMAX + i) * N + c], pos[((size_t)1 * KMAX + i) * N + c],
+                 pos[((size_t)2 * KMAX + i) * N + c]);
+      r[i] = grad_pos ? V3d(grad_pos[((size_t)0 * KMAX + i) * N + c], grad_pos[((size_t)1 * KMAX + i) * N + c],
+                            grad_pos[((size_t)2 * KMAX + i) * N + c])
+                      : V3d();
+    }
+    double gxD[3], gxL[3], gth[ADJ_P];
+    bool good = chain_gradient(s, p, n, type[c], get3d(xD, N, c), get3d(nD, N, c), get3d(xL, N, c), pr, x, r,
+                               grad_G ? grad_G[c] : 0.0, theta, gxD, gxL, gth);
+    if (!good) return;
+    ok[c] = 1;
+    for (int a = 0; a < 3; ++a) { grad_xD[(size_t)a * N + c] = gxD[a]; grad_xL[(size_t)a * N + c] = gxL[a]; }
+    for (int k = 0; k < P; ++k) grad_theta[(size_t)c * P + k] = gth[k];
   });
 }
 

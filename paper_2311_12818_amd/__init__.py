@@ -259,6 +259,20 @@ class Endpoints:
         self.type = _dev(ep.types, torch.uint8, device)
         self.obj1 = _dev(ep.obj1, torch.int32, device)
 
+    @classmethod
+    def from_tensors(cls, xD, nD, xL, length, types, obj1):
+        """Wrap device tensors ([3][N] float32 points / normal, [N] uint8
+        lengths and types, [N] int32 p_0 objects) without copying."""
+        self = cls.__new__(cls)
+        self.N = int(length.shape[0])
+        self.xD, self.nD, self.xL = xD.contiguous(), nD.contiguous(), xL.contiguous()
+        self.len, self.type, self.obj1 = length.contiguous(), types.contiguous(), obj1.contiguous()
+        for t, dt in ((self.xD, "float32"), (self.nD, "float32"), (self.xL, "float32"), (self.len, "uint8"),
+                      (self.type, "uint8"), (self.obj1, "int32")):
+            if str(t.dtype) != "torch." + dt or not t.is_cuda:
+                raise MPGError(f"Endpoints.from_tensors: expected a device tensor of {dt}, got {t.dtype}")
+        return self
+
     def c(self) -> mpg_endpoints:
         return mpg_endpoints(self.N, self.xD.data_ptr(), self.nD.data_ptr(), self.xL.data_ptr(),
                              self.len.data_ptr(), self.type.data_ptr(), self.obj1.data_ptr())

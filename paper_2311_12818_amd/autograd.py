@@ -1,0 +1,104 @@
+"""Differentiable manifold walks: a ``torch.autograd.Function`` whose forward
+is the batched walk (manifold_walk_batch + manifold_walk_fp64) and whose
+backward is manifold_walk_adjoint, the implicit-function-theorem adjoint of
+the converged chains (Sec. 5.2).
+
+Differentiable inputs are the shading points x_D [3, N], the light points
+x_L [3, N] and the height-field parameters theta [P] (amplitude, phase per
+sine).  Outputs are the converged vertices [3, K, N], the generalized geometry
+term G [N] and the walk status [N] (not differentiable).  Chains that do not
+converge have zero gradients.  A change of theta rebuilds the device scene
+through the caller's ``scene_factory(theta)``.
+"""
+from __future__ import annotations
+
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import (MPGError, Endpoints, Scene, empty_chains, manifold_walk_adjoint, manifold_walk_batch,
+               manifold_walk_fp64, walk_outputs)
+
+
+class WalkProblem:
+    """What a differentiable walk keeps fixed: how to build the scene for a
+    given theta, the walk parameters, the shading normals, lengths, types and
+    p_0 objects of the chains, and the seed chains every forward starts from."""
+
+    def __init__(self, scene_factory: Callable[[np.ndarray], Scene], params, nD, length, types, obj1, seed_prim,
+                 seed_pos, seed_status=None):
+        self.scene_factory = scene_factory
+        self.params = params
+        self.nD, self.length, self.types, self.obj1 = nD, length, types, obj1
+        self.seed_prim, self.seed_pos, self.seed_status = seed_prim, seed_pos, seed_status
+        self._theta = None
+        self._scene: Optional[Scene] = None
+
+    def scene(self, theta) -> Scene:
+        th = np.asarray(theta.detach().double().cpu().numpy() if hasattr(theta, "detach") else theta, np.float64)
+        if self._scene is None or self._theta is None or not np.array_equal(th, self._theta):
+            self._scene = self.scene_factory(th)
+            self._theta = th.copy()
+        if self._scene.n_params != th.shape[0]:
+            raise MPGError(f"theta has {th.shape[0]} entries, the scene has {self._scene.n_params} parameters")
+        return self._scene
+
+    def endpoints(self, xD, xL) -> Endpoints:
+        return Endpoints.from_tensors(xD.detach().float(), self.nD, xL.detach().float(), self.length, self.types,
+                                      self.obj1)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _function():
+    torch = _torch()
+
+    class ManifoldWalk(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, xD, xL, theta, problem: WalkProblem):
+            scene = problem.scene(theta)
+            ep = problem.endpoints(xD, xL)
+            prm = problem.params
+            prim, pos = empty_chains(ep.N, xD.device)
+            outs = walk_outputs(ep.N, xD.device)
+            manifold_walk_batch(scene, prm, ep, problem.seed_prim, problem.seed_pos, problem.seed_status,
+                                out_prim=prim, out_pos=pos, outs=outs)
+            manifold_walk_fp64(scene, prm, ep, prim, pos, outs)
+            ctx.problem, ctx.scene, ctx.ep = problem, scene, ep
+            ctx.theta_meta = (theta.shape, theta.dtype)
+            ctx.xD_dtype, ctx.xL_dtype = xD.dtype, xL.dtype
+            ctx.save_for_backward(prim, pos, outs["status"])
+            status = outs["status"]
+            ctx.mark_non_differentiable(status)
+            return pos, outs["G"], status
+
+        @staticmethod
+        def backward(ctx, grad_pos, grad_G, _grad_status):
+            prim, pos, status = ctx.saved_tensors
+            scene, ep = ctx.scene, ctx.ep
+            gp = None if grad_pos is None else grad_pos.float().contiguous()
+            gG = None if grad_G is None else grad_G.float().contiguous()
+            dev = pos.device
+            gth = torch.zeros(max(1, scene.n_params), dtype=torch.float32, device=dev)
+            gxD, gxL, gth = manifold_walk_adjoint(scene, ctx.problem.params, ep, prim, pos, status, gp, gG,
+                                                  grad_theta=gth)
+            shape, dtype = ctx.theta_meta
+            g_theta = gth[:scene.n_params].to(dtype).reshape(shape) if ctx.needs_input_grad[2] else None
+            return (gxD.to(ctx.xD_dtype) if ctx.needs_input_grad[0] else None,
+                    gxL.to(ctx.xL_dtype) if ctx.needs_input_grad[1] else None, g_theta, None)
+
+    return ManifoldWalk
+
+
+_FN = None
+
+
+def manifold_walk(xD, xL, theta, problem: WalkProblem):
+    """Differentiable batched walk: returns (pos [3, K, N], G [N], status [N])."""
+    global _FN
+    if _FN is None:
+        _FN = _function()
+    return _FN.apply(xD, xL, theta, problem)

@@ -54,6 +54,57 @@ typedef vec3<float> f3;
 typedef vec3<double> d3;
 __device__ __forceinline__ f3 ld3(const float4& v) { return {v.x, v.y, v.z}; }
 
+// Forward-mode dual number (value, one directional derivative) for the
+// adjoint: the same templated geometry / constraint / elimination code runs
+// on it to differentiate J and G along one direction at a time.
+struct dfloat {
+  float v, d;
+  __device__ __forceinline__ dfloat() : v(0.f), d(0.f) {}
+  __device__ __forceinline__ dfloat(float x) : v(x), d(0.f) {}  // NOLINT
+  __device__ __forceinline__ dfloat(float x, float y) : v(x), d(y) {}
+};
+__device__ __forceinline__ dfloat operator+(dfloat a, dfloat b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ dfloat operator-(dfloat a, dfloat b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ dfloat operator-(dfloat a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ dfloat operator*(dfloat a, dfloat b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ dfloat operator/(dfloat a, dfloat b) {
+  float q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ dfloat& operator+=(dfloat& a, dfloat b) { a = a + b; return a; }
+__device__ __forceinline__ dfloat& operator-=(dfloat& a, dfloat b) { a = a - b; return a; }
+__device__ __forceinline__ dfloat& operator*=(dfloat& a, dfloat b) { a = a * b; return a; }
+__device__ __forceinline__ bool operator<(dfloat a, dfloat b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>(dfloat a, dfloat b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<=(dfloat a, dfloat b) { return a.v <= b.v; }
+__device__ __forceinline__ bool operator>=(dfloat a, dfloat b) { return a.v >= b.v; }
+__device__ __forceinline__ dfloat rsq(dfloat a) {
+  float r = 1.0f / sqrtf(a.v);
+  return {r, -0.5f * a.d * r * r * r};
+}
+__device__ __forceinline__ dfloat sqr_t(dfloat a) {
+  float r = sqrtf(a.v);
+  return {r, 0.5f * a.d / r};
+}
+// float / double forms (the dual overloads below would otherwise hide them)
+__device__ __forceinline__ float fabs(float a) { return ::fabsf(a); }
+__device__ __forceinline__ double fabs(double a) { return ::fabs(a); }
+__device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
+__device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
+__device__ __forceinline__ float fmin(float a, float b) { return ::fminf(a, b); }
+__device__ __forceinline__ double fmin(double a, double b) { return ::fmin(a, b); }
+__device__ __forceinline__ float copysign(float a, float b) { return ::copysignf(a, b); }
+__device__ __forceinline__ double copysign(double a, double b) { return ::copysign(a, b); }
+__device__ __forceinline__ float fma(float a, float b, float c) { return ::fmaf(a, b, c); }
+__device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
+__device__ __forceinline__ dfloat fabs(dfloat a) { return a.v < 0.f ? -a : a; }
+__device__ __forceinline__ dfloat fmax(dfloat a, dfloat b) { return a.v >= b.v ? a : b; }
+__device__ __forceinline__ dfloat fmin(dfloat a, dfloat b) { return a.v <= b.v ? a : b; }
+__device__ __forceinline__ dfloat copysign(dfloat a, dfloat b) { return {copysignf(a.v, b.v), 0.f}; }
+__device__ __forceinline__ dfloat fma(dfloat a, dfloat b, dfloat c) { return a * b + c; }
+template <typename T> struct is_dual { static constexpr bool value = false; };
+template <> struct is_dual<dfloat> { static constexpr bool value = true; };
+
 // Orthonormal basis about a unit vector: Duff et al., "Building an
 // orthonormal basis, revisited", JCGT 6(1), 2017 (branchless form).
 template <typename T>
@@ -127,6 +178,20 @@ struct DevGuide {
   const float* chol;   // [cells][comps][3]
   float lo[3], hi[3];
   int res, comps, target_obj;
+};
+
+// Height field of the scene (the adjoint's surface parameters): triangles
+// [first_tri, first_tri + n_tris), vertices [first_vert, first_vert + n_verts),
+// parameters [param_base, param_base + 2 n_sines): (amplitude, phase) per sine.
+struct DevHF {
+  int first_vert, n_verts, first_tri, n_tris, n_sines, param_base;
+  float amp[8], freq[8], psi[8], phase[8];
+};
+// One parameter direction of the adjoint: sine s of height field hf, which =
+// 0 for its amplitude, 1 for its phase; hf < 0 for none.
+struct ThetaDir {
+  const DevHF* hf;
+  int s, which;
 };
 
 struct WalkParams {
@@ -308,8 +373,48 @@ struct Geo {
   int mat;
 };
 
+// d/dtheta of a height-field vertex position and unit normal (z = z0 +
+// sum a sin(f (cos psi x + sin psi y) + phi), n = normalize(-h_x, -h_y, 1)).
+__device__ __forceinline__ void hf_vertex_deriv(const DevHF& h, int s, int which, float x, float y, f3 n, f3& dP,
+                                                f3& dN) {
+  float hx = 0.f, hy = 0.f;
+  for (int k = 0; k < h.n_sines; ++k) {
+    float arg = h.freq[k] * (cosf(h.psi[k]) * x + sinf(h.psi[k]) * y) + h.phase[k];
+    float c = h.amp[k] * h.freq[k] * cosf(arg);
+    hx += c * cosf(h.psi[k]);
+    hy += c * sinf(h.psi[k]);
+  }
+  float arg = h.freq[s] * (cosf(h.psi[s]) * x + sinf(h.psi[s]) * y) + h.phase[s];
+  float dz, dfac;  // dz/dtheta and d(h_x, h_y)/dtheta = dfac (cos psi, sin psi)
+  if (which == 0) {
+    dz = sinf(arg);
+    dfac = h.freq[s] * cosf(arg);
+  } else {
+    dz = h.amp[s] * cosf(arg);
+    dfac = -h.amp[s] * h.freq[s] * sinf(arg);
+  }
+  dP = {0.f, 0.f, dz};
+  f3 dm = {-dfac * cosf(h.psi[s]), -dfac * sinf(h.psi[s]), 0.f};
+  float ilm = rsq(hx * hx + hy * hy + 1.0f);
+  dN = (dm - n * dot(n, dm)) * ilm;
+}
+
+template <typename T>
+__device__ __forceinline__ void theta_vertex(const DevScene& S, const ThetaDir* td, int vid, vec3<T>& P,
+                                             vec3<T>& N) {
+  if constexpr (is_dual<T>::value) {
+    if (td && vid >= td->hf->first_vert && vid < td->hf->first_vert + td->hf->n_verts) {
+      float4 p = S.vpos[vid], nn = S.vnrm[vid];
+      f3 dP, dN;
+      hf_vertex_deriv(*td->hf, td->s, td->which, p.x, p.y, ld3(nn), dP, dN);
+      P.x.d = dP.x; P.y.d = dP.y; P.z.d = dP.z;
+      N.x.d = dN.x; N.y.d = dN.y; N.z.d = dN.z;
+    }
+  }
+}
+
 template <typename T, bool DERIV>
-__device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> x) {
+__device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> x, const ThetaDir* td = nullptr) {
   Geo<T> g;
   g.x = x;
   int obj;
@@ -332,6 +437,9 @@ __device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> 
     obj = id.w;
     vec3<T> P0 = cvt<T>(ld3(S.vpos[id.x])), P1 = cvt<T>(ld3(S.vpos[id.y])), P2 = cvt<T>(ld3(S.vpos[id.z]));
     vec3<T> N0 = cvt<T>(ld3(S.vnrm[id.x])), N1 = cvt<T>(ld3(S.vnrm[id.y])), N2 = cvt<T>(ld3(S.vnrm[id.z]));
+    theta_vertex(S, td, id.x, P0, N0);
+    theta_vertex(S, td, id.y, P1, N1);
+    theta_vertex(S, td, id.z, P2, N2);
     vec3<T> E1 = P1 - P0, E2 = P2 - P0;
     T lenE1 = norm(E1);
     g.e1 = E1 * ((T)1 / lenE1);
@@ -472,6 +580,7 @@ struct Sweep {
   T G[N][4];        // D~_i^-1 U_i
   T Dinv_last[4];   // D~_n^-1
   vec3<T> gso_last, gto_last;
+  T Cv[N][2];       // the residual itself
   T c2, cinf;       // |C|_2^2, |C|_inf
   T cond;           // max |J| * max |D~^-1|
   T cmin;           // smallest incident / outgoing cosine along the chain
@@ -483,9 +592,10 @@ struct Sweep {
 // fly (block Thomas: D~_i = D_i - L_i G_{i-1}, r~_i = -C_i - L_i g_{i-1},
 // G_i = D~_i^-1 U_i, g_i = D~_i^-1 r~_i), then back-substitute
 // y_n = g_n, y_i = g_i - G_i y_{i+1}.  JAC = false evaluates C only.
-template <typename T, int N, bool JAC, class STK>
+template <typename T, int N, bool JAC, class STK, bool BACK = true>
 __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL, int type, const int* prim,
-                                      const vec3<T>* x, Sweep<T, N>& W, STK& stk) {
+                                      const vec3<T>* x, Sweep<T, N>& W, STK& stk,
+                                      const ThetaDir* td = nullptr) {
   T g[N][2];
   W.c2 = 0;
   W.cinf = 0;
@@ -493,9 +603,9 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
   W.cmin = 1;
   W.singular = false;
   T jmax = 0, imax = 0;
-  Geo<T> gc = load_geo<T, JAC>(S, prim[0], x[0]);
+  Geo<T> gc = load_geo<T, JAC>(S, prim[0], x[0], td);
   Geo<T> gn;
-  if (N > 1) gn = load_geo<T, JAC>(S, prim[1], x[1]);
+  if (N > 1) gn = load_geo<T, JAC>(S, prim[1], x[1], td);
   vec3<T> pe1 = gc.e1, pe2 = gc.e2;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -509,6 +619,8 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
     else stk.vj64();
     vertex_cj<T, JAC>(gc, xp, xn, ea, eb, pe1, pe2, N > 1 && i < N - 1 ? gn.e1 : gc.e1,
                       N > 1 && i < N - 1 ? gn.e2 : gc.e2, v);
+    W.Cv[i][0] = v.C0;
+    W.Cv[i][1] = v.C1;
     W.c2 += v.C0 * v.C0 + v.C1 * v.C1;
     W.cinf = fmax(W.cinf, fmax(fabs(v.C0), fabs(v.C1)));
     if (JAC) {
@@ -544,11 +656,12 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
     pe2 = gc.e2;
     if (i + 1 < N) {
       gc = gn;
-      if (i + 2 < N) gn = load_geo<T, JAC>(S, prim[i + 2 < N ? i + 2 : 0], x[i + 2 < N ? i + 2 : 0]);
+      if (i + 2 < N) gn = load_geo<T, JAC>(S, prim[i + 2 < N ? i + 2 : 0], x[i + 2 < N ? i + 2 : 0], td);
     }
   }
   if (!JAC) return;
   W.cond = jmax * imax;
+  if (!BACK) return;
   T y0 = g[N - 1][0], y1 = g[N - 1][1];
   vec3<T> f1, f2;
   load_frame(S, prim[N - 1], x[N - 1], f1, f2);

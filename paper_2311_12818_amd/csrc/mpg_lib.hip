@@ -39,6 +39,8 @@ struct mpg_scene {
   std::vector<void*> allocs;
   int n_nodes = 0, max_depth = 0, n_tris = 0, n_verts = 0;
   std::vector<mpg_heightfield> hfs;
+  const DevHF* dev_hf = nullptr;
+  int n_params = 0;
   float scale = 1.0f;
   int device = 0;
 };
@@ -127,6 +129,31 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
   s->n_tris = d->n_tris;
   s->n_verts = d->n_verts;
   for (int i = 0; i < d->n_heightfields; ++i) s->hfs.push_back(d->heightfields[i]);
+  std::vector<DevHF> dhf;
+  for (const mpg_heightfield& h : s->hfs) {
+    if (h.n_sines < 0 || h.n_sines > 8 || h.res < 2 || h.first_vert < 0 || h.first_tri < 0 ||
+        h.first_vert + h.res * h.res > d->n_verts || h.first_tri + 2 * (h.res - 1) * (h.res - 1) > d->n_tris) {
+      delete s;
+      return fail(MPG_ERR_INVALID_ARG, "mpg_scene_create: height field outside the mesh or more than 8 sines");
+    }
+    DevHF q;
+    std::memset(&q, 0, sizeof(q));
+    q.first_vert = h.first_vert;
+    q.n_verts = h.res * h.res;
+    q.first_tri = h.first_tri;
+    q.n_tris = 2 * (h.res - 1) * (h.res - 1);
+    q.n_sines = h.n_sines;
+    q.param_base = s->n_params;
+    for (int k = 0; k < h.n_sines; ++k) {
+      q.amp[k] = h.amp[k]; q.freq[k] = h.freq[k]; q.psi[k] = h.psi[k]; q.phase[k] = h.phase[k];
+    }
+    s->n_params += 2 * h.n_sines;
+    dhf.push_back(q);
+  }
+  if (s->n_params > 64) {
+    delete s;
+    return fail(MPG_ERR_UNSUPPORTED, "mpg_scene_create: more than 64 height-field parameters");
+  }
   auto bail = [&](hipError_t e, const char* what) {
     free_all(s->allocs);
     delete s;
@@ -244,6 +271,7 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
   if ((e = upload(s->allocs, &D.cdf_prim, cprim.data(), cprim.size())) != hipSuccess) return bail(e, "cdf prims");
   if ((e = upload(s->allocs, &D.cdf_range, crange.data(), crange.size())) != hipSuccess) return bail(e, "cdf ranges");
   if ((e = upload(s->allocs, &D.obj_bounds, ob.data(), ob.size())) != hipSuccess) return bail(e, "bounds");
+  if ((e = upload(s->allocs, &s->dev_hf, dhf.data(), dhf.size())) != hipSuccess) return bail(e, "height fields");
   *out = s;
   return MPG_OK;
 }
