@@ -47,9 +47,15 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="chains (default: the workload's size)")
     ap.add_argument("--form", default="persistent", choices=["plain", "persistent"])
     ap.add_argument("--compare-forms", type=int, default=1, help="also time the other form (fewer steps)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2311_12818_amd", "tuned.json"))
+    ap.add_argument("--graph", type=int, default=1, help="also time the step captured into a HIP graph")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a known-size kernel against which "
+                         "hardware byte counters are scaled)")
+    ap.add_argument("--adjoint-n", type=int, default=1 << 20,
+                    help="chains of the forward+adjoint leg on the differentiation workload (0 = skip)")
     return ap.parse_args()
 
 
@@ -75,7 +81,20 @@ def load_tuned(path, workload):
         return {}
 
 
-def cpu_baseline(name, sc, ep_fn, n_total, seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(name, sc, full, seconds, single_thread_seconds=4.0):
+    """The oracle (seeds + FP64 walk + polish) on the leading configurations of
+    the same batch the GPU walks, for a bounded time."""
     import numpy as np
 
     import oracle as O
@@ -83,20 +102,116 @@ def cpu_baseline(name, sc, ep_fn, n_total, seconds):
     threads = min(16, os.cpu_count() or 1)
     osc = O.Scene(sc)
     prm = O.params(sc.scale, cone_cos=math.cos(math.radians(W.SEED_CONE_DEG)))
-    full = ep_fn(min(n_total, 1 << 20))
-    chunk = 8192
-    done, conv, t0 = 0, 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds and done < full.n:
-        idx = np.arange(done, min(done + chunk, full.n))
-        ep = full.subset(idx)
-        prim, pos, st = O.sample_seeds(osc, ep, prm=prm, nthreads=threads)
-        r = O.walk(osc, ep, prim, pos.astype(np.float32), st, prm=prm, nthreads=threads)
-        conv += int((r["status"] == O.CONVERGED).sum())
-        done += len(idx)
-    el = time.perf_counter() - t0
+
+    def run(nthreads, budget, chunk):
+        done, conv, t0 = 0, 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget and done < full.n:
+            idx = np.arange(done, min(done + chunk, full.n))
+            ep = full.subset(idx)
+            prim, pos, st = O.sample_seeds(osc, ep, prm=prm, nthreads=nthreads)
+            r = O.walk(osc, ep, prim, pos.astype(np.float32), st, prm=prm, nthreads=nthreads)
+            conv += int((r["status"] == O.CONVERGED).sum())
+            done += len(idx)
+        return done, conv, time.perf_counter() - t0
+
+    done, conv, el = run(threads, seconds, 8192)
+    d1, c1, e1 = run(1, single_thread_seconds, 1024)
     return {"value": conv / el, "unit": "converged walks/s", "cores": threads, "kind": "oracle",
             "sample": f"first {done} configurations of the same {name} batch (oracle p_0 seeds + FP64 walk + polish, "
-                      f"{el:.1f} s on {threads} threads)"}
+                      f"{el:.1f} s on {threads} threads)",
+            "attempted_walks_per_s": done / el, "single_thread_converged_walks_per_s": c1 / e1,
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def graph_leg(M, prm, step, args, N):
+    """The same step captured once into a HIP graph (torch's graph API over the
+    library's stream-ordered calls) and replayed."""
+    import torch
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(prm)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            st = step(prm)
+        for _ in range(max(1, args.warmup)):
+            g.replay()
+        torch.cuda.synchronize()
+    except (RuntimeError, M.MPGError) as exc:
+        return {"error": str(exc)}
+    stream = torch.cuda.current_stream()
+    steps = max(1, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return {"ms_per_step": 1e3 * wall, "gpu_ms_per_step": e0.elapsed_time(e1) / steps, "graph_replays": steps}
+
+
+def adjoint_leg(M, W, args, tuned_all, cone):
+    """Forward walk + IFT adjoint on the differentiation workload: 2^20 chains
+    of length 2..4 through the slab stack, loss sum(r . x + g G) with fixed
+    random cotangents, gradients w.r.t. x_D, x_L and the 32 slab parameters."""
+    import torch
+    n = args.adjoint_n
+    sc = W.slab_stack_scene()
+    ep = W.slab_adjoint_endpoints(n)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    kw = dict(cone_cos=cone, max_len=4, defer_fp64=1, form=M.FORM_PERSISTENT)
+    for k in ("bucketing", "waves_per_group", "stack_depth", "refill"):
+        if k in tuned_all:
+            kw[k] = int(tuned_all[k])
+    prm = M.walk_params(sc.scale, **kw)
+    ws = M.Workspace(n)
+    prim, pos = M.empty_chains(n)
+    outs = M.walk_outputs(n)
+    r, g = W.loss_weights(n)
+    rt, gt = torch.as_tensor(r).cuda(), torch.as_tensor(g).cuda()
+    gxD = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    gxL = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    gth = torch.zeros(max(1, scene.n_params), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+        M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+
+    def adj():
+        gth.zero_()
+        M.manifold_walk_adjoint(scene, prm, dep, prim, pos, outs["status"], rt, gt, grad_xD=gxD, grad_xL=gxL,
+                                grad_theta=gth)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+        adj()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+        adj()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    conv = int((outs["status"] == M.CONVERGED).sum())
+    return {"workload": "slab_adjoint", "chains": n, "converged": conv, "ms_per_step": 1e3 * wall,
+            "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "converged_walks_per_s": conv / wall,
+            "adjoint_converged_chains_per_s": conv / (adj_ms / 1e3),
+            "theta_grad_norm": float(gth.norm())}
 
 
 def main():
@@ -113,6 +228,13 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        n_el = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     name = args.workload
     scene_fn, ep_fn = W.WORKLOADS[name]
     N = args.n or DEFAULT_N[name]
@@ -193,6 +315,12 @@ def main():
         except M.MPGError as exc:
             forms[other] = {"error": str(exc)}
 
+    forms[main_form]["attempted_walks_per_s"] = N / (R["ms_per_step"] / 1e3)
+    if args.graph:
+        forms[main_form + "+graph"] = graph_leg(M, params(main_form), step, args, N)
+    if args.adjoint_n > 0:
+        forms["+adjoint"] = adjoint_leg(M, W, args, tuned_all=load_tuned(args.tuned, "slab_adjoint"), cone=cone)
+
     # untimed counting pass: algorithmic work of one walk launch
     prm_c = params("plain")
     p, q, st = M.sample_seeds(scene, dep, prm_c)
@@ -237,7 +365,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(name, sc, ep_fn, N, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(name, sc, ep, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

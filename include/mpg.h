@@ -115,6 +115,19 @@ void mpg_scene_destroy(mpg_scene* scene);
 /* BVH statistics: node count, maximum depth (the traversal stack needs depth+1 entries). */
 mpg_status mpg_scene_stats(const mpg_scene* scene, int32_t* n_nodes, int32_t* max_depth, int32_t* n_tris);
 
+/* Replaces the height-field parameters theta -- the differentiable surface
+ * parameters of manifold_walk_adjoint (Sec. 5.2): d_theta is device float
+ * [n_params], n_params = 2 * sum of n_sines over the scene's height fields,
+ * amplitude then phase per sine in height-field order.  Height-field
+ * vertices and normals are recomputed (FP64 evaluation of the sine sum,
+ * stored in FP32), the BVH keeps its topology and every box is refitted to
+ * the triangles under it, and the per-object area tables used by p_0 and the
+ * scene top used by guided seeds are recomputed.  Synchronizes hip_stream
+ * (it reads theta back to validate it and the new scene top); no other work
+ * on this scene may be in flight.  Errors: n_params differs from the scene's
+ * count, NULL theta, non-finite theta. */
+mpg_status mpg_scene_set_params(mpg_scene* scene, const float* d_theta, int32_t n_params, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batches                                                                    */
 /* ------------------------------------------------------------------------ */
@@ -166,7 +179,8 @@ typedef struct {
   int32_t bucketing;         /* persistent form: sort chains by length first (1) or not (0) */
   int32_t waves_per_group;   /* wavefronts per workgroup (1, 2, 4) */
   int32_t stack_depth;       /* LDS traversal stack entries per lane (>= BVH depth + 1; 0 = automatic) */
-  int32_t refill;            /* persistent form: lanes pull a new chain as soon as theirs finishes (1) */
+  int32_t refill;            /* persistent form with bucketing: each lane takes a new chain as soon as its own
+                                finishes (1) instead of whole 64-chain batches (0, default) */
   int32_t max_len;           /* longest chain in the batch (1..8, default 8); longer chains get MPG_BAD_INPUT */
   int32_t defer_fp64;        /* 1: leave MPG_NEEDS_FP64 chains for a later manifold_walk_fp64 call (0) */
 } mpg_walk_params;

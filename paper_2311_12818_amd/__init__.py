@@ -182,6 +182,13 @@ class Scene:
         self.n_params = 2 * sum(len(hf.amp) for hf in sc.heightfields)
         self.src = sc
 
+    def set_params(self, theta):
+        """New height-field parameters (device float tensor [n_params]); see
+        mpg_scene_set_params."""
+        torch = _torch()
+        th = theta.detach().to(device="cuda", dtype=torch.float32).contiguous()
+        _check(lib().mpg_scene_set_params(self.h, th.data_ptr(), int(th.numel()), _stream()), "mpg_scene_set_params")
+
     def stats(self):
         a, b, c = I32(), I32(), I32()
         _check(lib().mpg_scene_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "mpg_scene_stats")

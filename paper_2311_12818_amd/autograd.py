@@ -7,40 +7,35 @@ Differentiable inputs are the shading points x_D [3, N], the light points
 x_L [3, N] and the height-field parameters theta [P] (amplitude, phase per
 sine).  Outputs are the converged vertices [3, K, N], the generalized geometry
 term G [N] and the walk status [N] (not differentiable).  Chains that do not
-converge have zero gradients.  A change of theta rebuilds the device scene
-through the caller's ``scene_factory(theta)``.
+converge have zero gradients.  A change of theta updates the device scene in
+place (mpg_scene_set_params: vertices, normals, BVH refit, area tables).
 """
 from __future__ import annotations
-
-from typing import Callable, Optional
-
-import numpy as np
 
 from . import (MPGError, Endpoints, Scene, empty_chains, manifold_walk_adjoint, manifold_walk_batch,
                manifold_walk_fp64, walk_outputs)
 
 
 class WalkProblem:
-    """What a differentiable walk keeps fixed: how to build the scene for a
-    given theta, the walk parameters, the shading normals, lengths, types and
-    p_0 objects of the chains, and the seed chains every forward starts from."""
+    """What a differentiable walk keeps fixed: the device scene (its
+    height-field parameters follow theta through mpg_scene_set_params), the
+    walk parameters, the shading normals, lengths, types and p_0 objects of
+    the chains, and the seed chains every forward starts from."""
 
-    def __init__(self, scene_factory: Callable[[np.ndarray], Scene], params, nD, length, types, obj1, seed_prim,
-                 seed_pos, seed_status=None):
-        self.scene_factory = scene_factory
+    def __init__(self, scene: Scene, params, nD, length, types, obj1, seed_prim, seed_pos, seed_status=None):
+        self._scene = scene
         self.params = params
         self.nD, self.length, self.types, self.obj1 = nD, length, types, obj1
         self.seed_prim, self.seed_pos, self.seed_status = seed_prim, seed_pos, seed_status
         self._theta = None
-        self._scene: Optional[Scene] = None
 
     def scene(self, theta) -> Scene:
-        th = np.asarray(theta.detach().double().cpu().numpy() if hasattr(theta, "detach") else theta, np.float64)
-        if self._scene is None or self._theta is None or not np.array_equal(th, self._theta):
-            self._scene = self.scene_factory(th)
-            self._theta = th.copy()
-        if self._scene.n_params != th.shape[0]:
-            raise MPGError(f"theta has {th.shape[0]} entries, the scene has {self._scene.n_params} parameters")
+        if theta.numel() != self._scene.n_params:
+            raise MPGError(f"theta has {theta.numel()} entries, the scene has {self._scene.n_params} parameters")
+        th = theta.detach().float()
+        if self._theta is None or not bool((th == self._theta).all()):
+            self._scene.set_params(th)
+            self._theta = th.clone()
         return self._scene
 
     def endpoints(self, xD, xL) -> Endpoints:
@@ -67,7 +62,8 @@ def _function():
             manifold_walk_batch(scene, prm, ep, problem.seed_prim, problem.seed_pos, problem.seed_status,
                                 out_prim=prim, out_pos=pos, outs=outs)
             manifold_walk_fp64(scene, prm, ep, prim, pos, outs)
-            ctx.problem, ctx.scene, ctx.ep = problem, scene, ep
+            ctx.problem, ctx.ep = problem, ep
+            ctx.theta_value = theta.detach().clone()
             ctx.theta_meta = (theta.shape, theta.dtype)
             ctx.xD_dtype, ctx.xL_dtype = xD.dtype, xL.dtype
             ctx.save_for_backward(prim, pos, outs["status"])
@@ -78,7 +74,8 @@ def _function():
         @staticmethod
         def backward(ctx, grad_pos, grad_G, _grad_status):
             prim, pos, status = ctx.saved_tensors
-            scene, ep = ctx.scene, ctx.ep
+            # the scene may have moved to another theta since this forward
+            scene, ep = ctx.problem.scene(ctx.theta_value), ctx.ep
             gp = None if grad_pos is None else grad_pos.float().contiguous()
             gG = None if grad_G is None else grad_G.float().contiguous()
             dev = pos.device

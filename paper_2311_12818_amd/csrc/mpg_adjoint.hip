@@ -1,3 +1,5 @@
+#include "mpg_internal.h"
+
 // Implicit-function-theorem adjoint of converged chains (continuity of the
 // specular manifold, Sec. 5.2): the converged local coordinates y* satisfy
 // C(y*, p) = 0 for the parameters p = (x_D, x_L, theta), so for a loss

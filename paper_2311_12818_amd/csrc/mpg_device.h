@@ -716,55 +716,87 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
 // |C|_2 decreases (then beta = min(1, 2 length)); a rejected full step that
 // was within tol_vertex L ends the walk as ST_NEEDS_FP64 (precision floor);
 // any other rejection sets beta = length / 2.
+// Walk state of one chain between trial steps.
+template <int N>
+struct WalkState {
+  int prim[N], obj[N];
+  f3 x[N], dl[N];
+  float beta, c2, step2;
+  int it;
+  bool need_jac;  // the Jacobian sweep at x is due before the next trial
+};
+
+template <int N>
+__device__ __forceinline__ void walk_begin(const DevScene& S, WalkState<N>& w) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) w.obj[i] = prim_obj(S, w.prim[i]);
+  w.beta = 1.0f;
+  w.it = 0;
+  w.need_jac = true;
+}
+
+// One step of a walk: the Jacobian sweep when due, then one trial.  Returns
+// the final status, or -1 while the walk goes on.  walk_core loops over it;
+// the lane-refill kernel interleaves it with taking new chains.
+template <int N, class STK>
+__device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type,
+                                         WalkState<N>& w, STK& stk) {
+  if (w.need_jac) {
+    Sweep<float, N> W;
+    sweep<float, N, true>(S, xD, xL, type, w.prim, w.x, W, stk);
+    if (W.singular) return ST_SINGULAR;
+    w.c2 = W.c2;
+    w.step2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      w.dl[i] = W.dl[i];
+      w.step2 = fmaxf(w.step2, dot(W.dl[i], W.dl[i]));
+    }
+    w.need_jac = false;
+  }
+  if (w.it >= P.max_iter) return ST_MAX_ITER;
+  ++w.it;
+  f3 xn[N];
+  int pn[N];
+  const bool small = w.step2 <= P.tol_step2;
+  const float bt = small ? 1.0f : w.beta;
+  if (!reproject<N>(S, xD, w.x, w.dl, bt, w.obj, P.tmin, stk, xn, pn)) {
+    w.beta = 0.5f * bt;
+    return -1;
+  }
+  Sweep<float, N> Wc;
+  sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc, stk);
+  const bool done = small && Wc.cinf <= P.tol_residual;
+  if (done || Wc.c2 < w.c2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) { w.x[i] = xn[i]; w.prim[i] = pn[i]; }
+    if (done) return ST_CONVERGED;
+    w.need_jac = true;
+    w.beta = fminf(1.0f, 2.0f * bt);
+    return -1;
+  }
+  // the full step is within tolerance but no longer lowers the residual:
+  // FP32 has reached its precision floor (e.g. near-grazing half vectors);
+  // the FP64 pass decides
+  if (small) return ST_NEEDS_FP64;
+  w.beta = 0.5f * bt;
+  return -1;
+}
+
 template <int N, class STK>
 __device__ __forceinline__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type, int* prim, f3* x,
                          int& iters, STK& stk) {
-  int obj[N];
+  WalkState<N> w;
 #pragma unroll
-  for (int i = 0; i < N; ++i) obj[i] = prim_obj(S, prim[i]);
-  Sweep<float, N> W;
-  sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
-  iters = 0;
-  if (W.singular) return ST_SINGULAR;
-  float beta = 1.0f;
-  float c2 = W.c2;
-  float step2 = 0.0f;
-#pragma unroll
-  for (int i = 0; i < N; ++i) step2 = fmaxf(step2, dot(W.dl[i], W.dl[i]));
-  for (int it = 1; it <= P.max_iter; ++it) {
-    iters = it;
-    f3 xn[N];
-    int pn[N];
-    bool small = step2 <= P.tol_step2;
-    float bt = small ? 1.0f : beta;
-    if (!reproject<N>(S, xD, x, W.dl, bt, obj, P.tmin, stk, xn, pn)) {
-      beta = 0.5f * bt;
-      continue;
-    }
-    Sweep<float, N> Wc;
-    sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc, stk);
-    bool done = small && Wc.cinf <= P.tol_residual;
-    if (done || Wc.c2 < c2) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) { x[i] = xn[i]; prim[i] = pn[i]; }
-      if (done) return ST_CONVERGED;
-      sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
-      if (W.singular) return ST_SINGULAR;
-      c2 = W.c2;
-      step2 = 0.0f;
-#pragma unroll
-      for (int i = 0; i < N; ++i) step2 = fmaxf(step2, dot(W.dl[i], W.dl[i]));
-      beta = fminf(1.0f, 2.0f * bt);
-    } else if (small) {
-      // the full step is within tolerance but no longer lowers the residual:
-      // FP32 has reached its precision floor (e.g. near-grazing half vectors);
-      // the FP64 pass decides
-      return ST_NEEDS_FP64;
-    } else {
-      beta = 0.5f * bt;
-    }
+  for (int i = 0; i < N; ++i) { w.prim[i] = prim[i]; w.x[i] = x[i]; }
+  walk_begin<N>(S, w);
+  int st;
+  while ((st = walk_step<N>(S, P, xD, xL, type, w, stk)) < 0) {
   }
-  return ST_MAX_ITER;
+#pragma unroll
+  for (int i = 0; i < N; ++i) { prim[i] = w.prim[i]; x[i] = w.x[i]; }
+  iters = w.it;
+  return st;
 }
 
 // Unpolarized Fresnel reflectance of a smooth dielectric (textbook form).

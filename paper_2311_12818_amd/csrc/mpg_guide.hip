@@ -1,3 +1,5 @@
+#include "mpg_internal.h"
+
 // Guide handles and fit_guide (weighted EM per cell).
 extern "C" mpg_status mpg_guide_create(const mpg_guide_desc* d, mpg_guide** out) {
   if (!d || !out) return fail(MPG_ERR_INVALID_ARG, "mpg_guide_create: NULL argument");

@@ -1,98 +1,18 @@
 // libmpg: kernels and the C ABI declared in include/mpg.h.
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <mutex>
-#include <string>
-#include <vector>
-
-#include "../../include/mpg.h"
-#include "mpg_device.h"
-#include "mpg_scene.h"
-
-using namespace mpg;
+#include "mpg_internal.h"
+#include "mpg_walk.h"
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
-static mpg_status fail(mpg_status code, const std::string& msg) {
+mpg_status fail(mpg_status code, const std::string& msg) {
   g_err = msg;
   return code;
 }
-#define HIP_TRY(expr)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess) return fail(MPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 extern "C" const char* mpg_last_error(void) { return g_err.c_str(); }
 extern "C" const char* mpg_version(void) { return "mpg 0.1 gfx950"; }
-
-// ---------------------------------------------------------------------------
-// handles
-// ---------------------------------------------------------------------------
-struct mpg_scene {
-  DevScene dev;
-  std::vector<void*> allocs;
-  int n_nodes = 0, max_depth = 0, n_tris = 0, n_verts = 0;
-  std::vector<mpg_heightfield> hfs;
-  const DevHF* dev_hf = nullptr;
-  int n_params = 0;
-  float scale = 1.0f;
-  int device = 0;
-};
-
-struct mpg_workspace {
-  int32_t cap = 0;
-  int32_t* perm = nullptr;     // [cap] chain order for the persistent form
-  int32_t* counters = nullptr; // [64] histogram / offsets / queue heads
-  int32_t* aux = nullptr;      // [cap] scratch (sample cell ids, sorted indices)
-  std::vector<void*> allocs;
-};
-
-struct mpg_guide {
-  mpg_guide_desc desc;
-  int cells = 0;
-  int32_t* valid = nullptr;
-  float* pi = nullptr;
-  float* mu = nullptr;
-  float* cov = nullptr;
-  float* chol = nullptr;
-  int32_t* count = nullptr;
-  int32_t* scratch = nullptr;  // fit_guide per-cell offsets and cursors
-  std::vector<void*> allocs;
-  DevGuide dev() const {
-    DevGuide g;
-    g.valid = valid; g.pi = pi; g.mu = mu; g.chol = chol;
-    for (int a = 0; a < 3; ++a) { g.lo[a] = desc.lo[a]; g.hi[a] = desc.hi[a]; }
-    g.res = desc.res; g.comps = desc.comps; g.target_obj = desc.target_obj;
-    return g;
-  }
-};
-
-template <class T>
-static hipError_t dalloc(std::vector<void*>& list, T** p, size_t count) {
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
-  if (e == hipSuccess) { list.push_back(q); *p = (T*)q; }
-  return e;
-}
-template <class T>
-static hipError_t upload(std::vector<void*>& list, const T** p, const T* host, size_t count) {
-  T* q = nullptr;
-  hipError_t e = dalloc(list, &q, count);
-  if (e != hipSuccess) return e;
-  if (count) e = hipMemcpy(q, host, count * sizeof(T), hipMemcpyHostToDevice);
-  *p = q;
-  return e;
-}
-static void free_all(std::vector<void*>& list) {
-  for (void* p : list) (void)hipFree(p);
-  list.clear();
-}
 
 // ---------------------------------------------------------------------------
 // scene
@@ -180,14 +100,29 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     for (int k = 0; k < 3; ++k) zmax = std::max(zmax, d->verts[3 * d->tris[3 * t + k] + 2]);
   }
   std::vector<float> nodes;
-  std::vector<int32_t> order;
+  std::vector<int32_t> order, ranges;
   int depth = 0;
   int n_nodes = 0;
   if (d->n_tris > 0) {
     float lo = INFINITY, hi = -INFINITY;
     for (int i = 0; i < 3 * d->n_verts; ++i) { lo = std::min(lo, d->verts[i]); hi = std::max(hi, d->verts[i]); }
     float pad = 1e-6f * std::max(1.0f, std::max(std::fabs(lo), std::fabs(hi)));
-    n_nodes = mpg_host::build_bvh(d->verts, d->tris, d->n_tris, pad, nodes, order, &depth);
+    s->pad = pad;
+    n_nodes = mpg_host::build_bvh(d->verts, d->tris, d->n_tris, pad, nodes, order, ranges, &depth);
+  }
+  s->n_objects = d->n_objects;
+  // top of the geometry that the height-field parameters do not move
+  {
+    std::vector<char> moving(d->n_verts, 0);
+    for (const mpg_heightfield& h : s->hfs)
+      for (int v = h.first_vert; v < h.first_vert + h.res * h.res; ++v) moving[v] = 1;
+    for (int t = 0; t < d->n_tris; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int v = d->tris[3 * t + k];
+        if (!moving[v]) s->zmax_static = std::max(s->zmax_static, d->verts[3 * v + 2]);
+      }
+    for (int k = 0; k < d->n_spheres; ++k)
+      s->zmax_static = std::max(s->zmax_static, d->spheres[4 * k + 2] + d->spheres[4 * k + 3]);
   }
   s->n_nodes = n_nodes;
   s->max_depth = depth;
@@ -272,6 +207,9 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
   if ((e = upload(s->allocs, &D.cdf_range, crange.data(), crange.size())) != hipSuccess) return bail(e, "cdf ranges");
   if ((e = upload(s->allocs, &D.obj_bounds, ob.data(), ob.size())) != hipSuccess) return bail(e, "bounds");
   if ((e = upload(s->allocs, &s->dev_hf, dhf.data(), dhf.size())) != hipSuccess) return bail(e, "height fields");
+  if ((e = upload(s->allocs, &s->order, order.data(), order.size())) != hipSuccess) return bail(e, "leaf order");
+  if ((e = upload(s->allocs, &s->ranges, ranges.data(), ranges.size())) != hipSuccess) return bail(e, "node ranges");
+  if ((e = dalloc(s->allocs, &s->zmax_bits, 1)) != hipSuccess) return bail(e, "scratch");
   *out = s;
   return MPG_OK;
 }
@@ -305,7 +243,7 @@ extern "C" mpg_status mpg_walk_params_default(float scale, mpg_walk_params* p) {
   p->bucketing = 1;
   p->waves_per_group = 4;
   p->stack_depth = 0;
-  p->refill = 1;
+  p->refill = 0;
   p->max_len = KMAX;
   p->defer_fp64 = 0;
   return MPG_OK;
@@ -338,25 +276,6 @@ extern "C" void mpg_workspace_destroy(mpg_workspace* w) {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-struct EpView {
-  const float* xD;
-  const float* nD;
-  const float* xL;
-  const uint8_t* len;
-  const uint8_t* type;
-  const int32_t* obj1;
-  int N;
-};
-__device__ __forceinline__ f3 ld_pt(const float* a, int N, int i) { return {a[i], a[N + i], a[2 * (size_t)N + i]}; }
-__device__ __forceinline__ bool finite3(f3 v) { return isfinite(v.x) && isfinite(v.y) && isfinite(v.z); }
-
-__device__ __forceinline__ Stack lane_stack(int depth) {
-  extern __shared__ int lds_stack[];
-  int lane = threadIdx.x & 63;
-  int wave = threadIdx.x >> 6;
-  return Stack{lds_stack + (size_t)wave * depth * 64 + lane, depth};
-}
-
 template <int N, class STK>
 __device__ __forceinline__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
                          uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
@@ -399,102 +318,6 @@ __global__ void k_sample_seeds(DevScene S, DevGuide G, int has_guide, WalkParams
   }
 }
 
-struct WalkIO {
-  const int32_t* seed_prim;
-  const float* seed_pos;
-  const int8_t* seed_status;
-  int32_t* prim_out;
-  float* pos_out;
-  int8_t* status;
-  uint8_t* iters;
-  uint64_t* sol;
-  float* G;
-  float* kappa;
-  float* resid;
-};
-
-template <int N, class STK>
-__device__ __forceinline__ void walk_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
-                         STK& stk) {
-  const size_t NN = E.N;
-  int prim[N];
-  f3 x[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    prim[i] = io.seed_prim[i * NN + c];
-    x[i] = {io.seed_pos[(0 * KMAX + i) * NN + c], io.seed_pos[(1 * KMAX + i) * NN + c],
-            io.seed_pos[(2 * KMAX + i) * NN + c]};
-  }
-  WalkOut R;
-  R.status = ST_SEED_INVALID;
-  R.iters = 0;
-  R.sol = 0;
-  R.G = 0.f;
-  R.kappa = 0.f;
-  R.resid = 0.f;
-  f3 xD = ld_pt(E.xD, E.N, c), xL = ld_pt(E.xL, E.N, c), nD = ld_pt(E.nD, E.N, c);
-  int type = E.type[c];
-  bool seed_ok = !(io.seed_status && io.seed_status[c] != 0);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    bool inr = prim[i] >= 0 ? prim[i] < S.n_tris : (prim[i] != PRIM_NONE && -1 - prim[i] < S.n_spheres);
-    seed_ok = seed_ok && inr && finite3(x[i]);
-  }
-  if (seed_ok) {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-      if (((type >> i) & 1) && S.obj_info[prim_obj(S, prim[i])].x != MAT_DIELECTRIC) seed_ok = false;
-  }
-  if (seed_ok) {
-    int it = 0;
-    R.status = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
-    R.iters = it;
-    // converged chains are finished by the finish pass (FP32) and, when
-    // flagged there or stalled here, by the FP64 pass
-    if (R.status == ST_CONVERGED) R.status = ST_PENDING;
-  }
-  io.status[c] = (int8_t)R.status;
-  if (io.iters) io.iters[c] = (uint8_t)R.iters;
-  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
-  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
-  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
-  if (io.resid) io.resid[c] = R.resid;
-  bool have = seed_ok;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    io.prim_out[i * NN + c] = have ? prim[i] : PRIM_NONE;
-    io.pos_out[(0 * KMAX + i) * NN + c] = have ? x[i].x : 0.f;
-    io.pos_out[(1 * KMAX + i) * NN + c] = have ? x[i].y : 0.f;
-    io.pos_out[(2 * KMAX + i) * NN + c] = have ? x[i].z : 0.f;
-  }
-}
-
-template <int NMAX, class STK>
-__device__ __forceinline__ void walk_dispatch(const DevScene& S, const WalkParams& P, const EpView& E,
-                                              const WalkIO& io, int c, STK& stk) {
-  int n = E.len[c];
-  if (n < 1 || n > NMAX || !finite3(ld_pt(E.xD, E.N, c)) || !finite3(ld_pt(E.xL, E.N, c)) ||
-      !finite3(ld_pt(E.nD, E.N, c))) {
-    io.status[c] = ST_BAD_INPUT;
-    if (io.iters) io.iters[c] = 0;
-    if (io.sol) io.sol[c] = 0;
-    if (io.G) io.G[c] = 0.f;
-    if (io.kappa) io.kappa[c] = 0.f;
-    if (io.resid) io.resid[c] = 0.f;
-    return;
-  }
-  switch (n) {
-    case 1: walk_one<1>(S, P, E, io, c, stk); break;
-    case 2: if (NMAX >= 2) walk_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
-    case 3: if (NMAX >= 3) walk_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
-    case 4: if (NMAX >= 4) walk_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
-    case 5: if (NMAX >= 5) walk_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
-    case 6: if (NMAX >= 6) walk_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
-    case 7: if (NMAX >= 7) walk_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
-    default: if (NMAX >= 8) walk_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
-  }
-}
-
 // Plain form: one launch, one chain per lane, chains in input order; NMAX is
 // the longest chain the launch handles (the register budget follows it).
 template <int NMAX>
@@ -503,48 +326,6 @@ __global__ void __launch_bounds__(256) k_walk_plain(DevScene S, WalkParams P, Ep
   Stack stk = lane_stack(P.depth);
   if (c >= E.N) return;
   walk_dispatch<NMAX>(S, P, E, io, c, stk);
-}
-
-// Finish pass over the chains the walk left as ST_PENDING (FP32 side and
-// visibility tests, kappa, G; near-singular or grazing chains become
-// ST_NEEDS_FP64).
-template <int N, class STK>
-__device__ __forceinline__ void finish_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
-                           STK& stk) {
-  const size_t NN = E.N;
-  int prim[N];
-  f3 x[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    prim[i] = io.prim_out[i * NN + c];
-    x[i] = {io.pos_out[(0 * KMAX + i) * NN + c], io.pos_out[(1 * KMAX + i) * NN + c],
-            io.pos_out[(2 * KMAX + i) * NN + c]};
-  }
-  WalkOut R;
-  R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
-  finish<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
-  io.status[c] = (int8_t)R.status;
-  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
-  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
-  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
-  if (io.resid) io.resid[c] = R.resid;
-}
-
-template <int NMAX, class STK>
-__device__ __forceinline__ void finish_dispatch(const DevScene& S, const WalkParams& P, const EpView& E,
-                                                const WalkIO& io, int c, STK& stk) {
-  if (io.status[c] != ST_PENDING) return;
-  int n = E.len[c];
-  switch (n) {
-    case 1: finish_one<1>(S, P, E, io, c, stk); break;
-    case 2: if (NMAX >= 2) finish_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
-    case 3: if (NMAX >= 3) finish_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
-    case 4: if (NMAX >= 4) finish_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
-    case 5: if (NMAX >= 5) finish_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
-    case 6: if (NMAX >= 6) finish_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
-    case 7: if (NMAX >= 7) finish_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
-    default: if (NMAX >= 8) finish_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
-  }
 }
 
 template <int NMAX>
@@ -697,6 +478,14 @@ static walk_kernel_t fp64_kernel(int nmax) {
   }
 }
 
+mpg_status launch_finish_plain(const mpg_scene* s, const WalkParams& P, const EpView& E, const WalkIO& io,
+                               int max_len, int threads, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(finish_kernel(max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds, stream,
+                     s->dev, P, E, io);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Bernoulli trials (Sec. 5.8)
 // ---------------------------------------------------------------------------
@@ -783,7 +572,7 @@ __global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int ha
 // ---------------------------------------------------------------------------
 // host entry points
 // ---------------------------------------------------------------------------
-static mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams* w, int* waves) {
+mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams* w, int* waves) {
   if (!p) return fail(MPG_ERR_INVALID_ARG, "NULL walk params");
   if (p->max_iter < 0 || p->max_iter > 255) return fail(MPG_ERR_INVALID_ARG, "max_iter outside 0..255");
   if (!(p->scale > 0.0f)) return fail(MPG_ERR_INVALID_ARG, "scale must be positive");
@@ -812,7 +601,7 @@ static mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, Wal
   return MPG_OK;
 }
 
-static mpg_status check_endpoints(const mpg_endpoints* e, EpView* v) {
+mpg_status check_endpoints(const mpg_endpoints* e, EpView* v) {
   if (!e) return fail(MPG_ERR_INVALID_ARG, "NULL endpoints");
   if (e->N < 0) return fail(MPG_ERR_INVALID_ARG, "N < 0");
   if (e->N > 0 && (!e->d_xD || !e->d_nD || !e->d_xL || !e->d_len || !e->d_type || !e->d_obj1))
@@ -847,8 +636,6 @@ extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const
   return MPG_OK;
 }
 
-mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
-                           int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream);
 
 extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
                                           const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
@@ -978,7 +765,3 @@ extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, 
   return MPG_OK;
 }
 
-// persistent form, guide fitting and the adjoint live in their own files
-#include "mpg_persistent.inc"
-#include "mpg_guide.inc"
-#include "mpg_adjoint.inc"

@@ -1,3 +1,6 @@
+#include "mpg_internal.h"
+#include "mpg_walk.h"
+
 // Persistent batched form of manifold_walk_batch.
 //
 // 1. k_bucket_hist: chains are classified by length n (invalid ones are
@@ -106,6 +109,66 @@ __global__ void __launch_bounds__(256) k_walk_persist(DevScene S, WalkParams P, 
   }
 }
 
+// Lane-refill walk of one length bucket.  Each lane owns one chain at a time
+// and advances it by one walk_step per turn of the loop (the routine the
+// plain form's walk_core loops over, so results are identical); a lane whose chain has
+// finished takes the next chain of the bucket in the same turn, so lanes do
+// not idle while the slowest chain of a 64-chain batch finishes.  Idle lanes
+// of a wavefront share one queue atomic per turn and take consecutive slots
+// by their rank in the ballot.  Every lane's chain ends within max_iter
+// trials and the queue is finite, so every wavefront leaves the loop.
+template <int N>
+__global__ void __launch_bounds__(256) k_walk_refill(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr,
+                                                     const int* perm) {
+  Stack stk = lane_stack(P.depth);
+  const int start = ctr[CTR_OFF + N];
+  const int count = ctr[CTR_HIST + N];
+  int* head = &ctr[CTR_HEAD + N - 1];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int c = -1;
+  bool drained = false;  // wave-uniform: the queue has no slot left for this wavefront
+  WalkState<N> w;
+  f3 xD = {0.f, 0.f, 0.f}, xL = {0.f, 0.f, 0.f};
+  int type = 0;
+  for (;;) {
+    const unsigned long long idle = __ballot(c < 0);
+    if (idle && !drained) {
+      const int nidle = __popcll(idle);
+      int base = 0;
+      if (lane == 0) base = atomicAdd(head, nidle);
+      base = __shfl(base, 0, 64);
+      if (c < 0) {
+        const int slot = base + __popcll(idle & below);
+        if (slot < count) {
+          c = perm[start + slot];
+          type = E.type[c];
+          xD = ld_pt(E.xD, E.N, c);
+          xL = ld_pt(E.xL, E.N, c);
+          if (load_seed<N>(S, E, io, c, type, w.prim, w.x)) {
+            walk_begin<N>(S, w);
+          } else {
+            store_walk<N>(E, io, c, ST_SEED_INVALID, 0, false, w.prim, w.x);
+            c = -1;
+          }
+        }
+      }
+      if (base + nidle >= count) drained = true;
+    }
+    if (__ballot(c >= 0) == 0) {
+      if (drained) break;
+      continue;
+    }
+    if (c >= 0) {
+      const int st = walk_step<N>(S, P, xD, xL, type, w, stk);
+      if (st >= 0) {
+        store_walk<N>(E, io, c, st, w.it, true, w.prim, w.x);
+        c = -1;
+      }
+    }
+  }
+}
+
 // Finish pass of one length bucket (same queue scheme, second head).
 template <int N>
 __global__ void __launch_bounds__(256) k_finish_persist(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr,
@@ -162,6 +225,18 @@ static persist_kernel_t persist_kernel(int n) {
     default: return k_walk_persist<8>;
   }
 }
+static persist_kernel_t refill_kernel(int n) {
+  switch (n) {
+    case 1: return k_walk_refill<1>;
+    case 2: return k_walk_refill<2>;
+    case 3: return k_walk_refill<3>;
+    case 4: return k_walk_refill<4>;
+    case 5: return k_walk_refill<5>;
+    case 6: return k_walk_refill<6>;
+    case 7: return k_walk_refill<7>;
+    default: return k_walk_refill<8>;
+  }
+}
 static mixed_kernel_t mixed_kernel(int nmax) {
   switch (nmax) {
     case 1: return k_walk_persist_mixed<1>;
@@ -216,7 +291,6 @@ static mpg_status side_streams(SideStreams** out) {
 
 mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
                            int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream) {
-  (void)refill;
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
   const int blocks = (E.N + 255) / 256;
@@ -228,10 +302,7 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
     int grid = resident_blocks((const void*)k, threads, lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, stream, s->dev, P, E, io, ctr);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(finish_kernel(max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds, stream,
-                       s->dev, P, E, io);
-    HIP_TRY(hipGetLastError());
-    return MPG_OK;
+    return launch_finish_plain(s, P, E, io, max_len, threads, lds, stream);
   }
   int8_t* cls = (int8_t*)ws->aux;
   hipLaunchKernelGGL(k_bucket_hist, dim3(blocks), dim3(256), 0, stream, E, io, max_len, ctr, cls);
@@ -248,7 +319,7 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   // lengths round-robin over the side streams, longest first; each length's
   // finish pass follows its walk on the same stream
   for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) & 3) {
-    persist_kernel_t k = persist_kernel(n);
+    persist_kernel_t k = refill ? refill_kernel(n) : persist_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
     HIP_TRY(hipGetLastError());

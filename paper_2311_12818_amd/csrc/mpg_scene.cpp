@@ -43,7 +43,7 @@ constexpr int kBins = 16;
 }  // namespace
 
 int build_bvh(const float* verts, const int32_t* tris, int n_tris, float pad, std::vector<float>& gpu_nodes,
-              std::vector<int32_t>& order, int* max_depth) {
+              std::vector<int32_t>& order, std::vector<int32_t>& ranges, int* max_depth) {
   std::vector<Box> tb(n_tris);
   std::vector<float> cen(3 * (size_t)n_tris);
   for (int t = 0; t < n_tris; ++t) {
@@ -136,6 +136,7 @@ int build_bvh(const float* verts, const int32_t* tris, int n_tris, float pad, st
       if (tree[i].left >= 0) { gidx[i] = n_int++; depth = std::max(depth, tree[i].depth); }
   }
   gpu_nodes.assign((size_t)n_int * 16, 0.0f);
+  ranges.assign((size_t)n_int * 4, 0);
   auto ref_of = [&](int ti) -> int32_t {
     const TreeNode& t = tree[ti];
     if (t.left >= 0) return gidx[ti];
@@ -162,10 +163,17 @@ int build_bvh(const float* verts, const int32_t* tris, int n_tris, float pad, st
     int32_t lref = (int32_t)(0x80000000u | ((uint32_t)tree[0].count << 24) | (uint32_t)tree[0].start);
     int32_t rref = (int32_t)0x80000000u;  // empty leaf
     put(0, tree[0].box, empty, lref, rref);
+    ranges[0] = tree[0].start;
+    ranges[1] = tree[0].count;
   } else {
     for (size_t i = 0; i < tree.size(); ++i) {
       if (tree[i].left < 0) continue;
       put(gidx[i], tree[tree[i].left].box, tree[tree[i].right].box, ref_of(tree[i].left), ref_of(tree[i].right));
+      int32_t* r = &ranges[(size_t)gidx[i] * 4];
+      r[0] = tree[tree[i].left].start;
+      r[1] = tree[tree[i].left].count;
+      r[2] = tree[tree[i].right].start;
+      r[3] = tree[tree[i].right].count;
     }
   }
   *max_depth = depth;

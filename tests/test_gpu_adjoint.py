@@ -206,9 +206,14 @@ def test_autograd_function_matches_central_differences(mpg):
     ep = W.slab_adjoint_endpoints(n, seed=7)
     osc = O.Scene(sc0)
     sprim, spos, sst = GC.oracle_seeds(osc, ep)
-    prm = M.walk_params(sc0.scale, cone_cos=GC.cone_cos(), max_len=4, defer_fp64=1)
+    # every converged chain takes the FP64 pass (graze threshold above 1), so
+    # the forward's vertices are Newton-polished in FP64 and G is evaluated in
+    # FP64: differences of re-solved chains then resolve h = 1e-4 (FP32
+    # vertices alone carry ~1e-6 of convergence slack, and FP32 G up to 1e-3
+    # relative at poorly conditioned chains)
+    prm = M.walk_params(sc0.scale, cone_cos=GC.cone_cos(), max_len=4, defer_fp64=1, fp64_graze_cos=2.0)
     dev = "cuda"
-    problem = WalkProblem(lambda th: M.Scene(W.slab_stack_scene(theta=th)), prm,
+    problem = WalkProblem(M.Scene(sc0), prm,
                           torch.as_tensor(ep.nD).to(dev), torch.as_tensor(ep.length).to(dev),
                           torch.as_tensor(ep.types).to(dev), torch.as_tensor(ep.obj1).to(dev),
                           torch.as_tensor(sprim).to(dev), torch.as_tensor(spos).to(dev),
@@ -219,18 +224,14 @@ def test_autograd_function_matches_central_differences(mpg):
     r, g = W.loss_weights(n, seed=8)
     rt, gt = torch.as_tensor(r).to(dev), torch.as_tensor(g).to(dev)
     pos, G, st = manifold_walk(xD, xL, theta, problem)
-    conv = st == 0
-    assert int(conv.sum()) >= 32
+    base_conv = st == 0
+    assert int(base_conv.sum()) >= 32
     zero = torch.zeros((), device=dev)
-    loss = torch.where(conv, (pos * rt).sum((0, 1)) + G * gt, zero).sum()
-    loss.backward()
-    base_conv = conv.clone()
 
-    def f(dxD, dxL, dth):
+    def per_chain(dxD, dxL, dth):
         with torch.no_grad():
             p, Gv, s = manifold_walk(xD + dxD, xL + dxL, theta + dth, problem)
-            assert torch.equal(s == 0, base_conv)
-            return float(torch.where(base_conv, (p * rt).sum((0, 1)) + Gv * gt, zero).double().sum())
+            return ((p * rt).sum((0, 1)) + Gv * gt).double(), s == 0
 
     gen = torch.Generator(device="cpu").manual_seed(0)
     for which in ("xD", "xL", "theta"):
@@ -239,13 +240,23 @@ def test_autograd_function_matches_central_differences(mpg):
             u = torch.randn(shape, generator=gen, dtype=torch.float32).to(dev)
             if which == "theta":
                 u[16:] = 0
-            h = 1e-3
+            h = 1e-4
             z3 = torch.zeros_like(xD)
             zt = torch.zeros_like(theta)
             args_p = (h * u if which == "xD" else z3, h * u if which == "xL" else z3, h * u if which == "theta" else zt)
             args_m = tuple(-a for a in args_p)
-            fd = (f(*args_p) - f(*args_m)) / (2 * h)
-            grad = {"xD": xD.grad, "xL": xL.grad, "theta": theta.grad}[which]
+            lp, cp = per_chain(*args_p)
+            lm, cm = per_chain(*args_m)
+            # chains that stay converged on both sides (a perturbation may push
+            # a chain across the FP32 convergence floor)
+            keep = base_conv & cp & cm
+            assert int(keep.sum()) >= 0.9 * int(base_conv.sum())
+            fd = float(torch.where(keep, lp - lm, zero.double()).sum()) / (2 * h)
+            # the adjoint of the same masked loss through the autograd function
+            pos, G, st = manifold_walk(xD, xL, theta, problem)
+            loss = torch.where(keep, (pos * rt).sum((0, 1)) + G * gt, zero).sum()
+            inp = {"xD": xD, "xL": xL, "theta": theta}[which]
+            (grad,) = torch.autograd.grad(loss, [inp])
             an = float((grad * u).double().sum())
-            print(dict(which=which, fd=fd, adjoint=an), flush=True)
+            print(dict(which=which, kept=int(keep.sum()), fd=fd, adjoint=an), flush=True)
             assert an == pytest.approx(fd, rel=1e-2, abs=0.05)

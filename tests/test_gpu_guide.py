@@ -47,15 +47,18 @@ def fit_both(mpg, samples, lo, hi, res, iters=30):
 
 
 def cell_ll(samples, lo, hi, res, pi, mu, cov, cells):
-    """Mean log-likelihood of each cell's samples under a fitted mixture."""
+    """Weighted mean log-likelihood of each cell's samples (weight > 0,
+    finite records, as the fit uses them) under a fitted mixture."""
     s = samples.astype(np.float64)
+    use = (s[:, 5] > 0) & np.isfinite(s[:, :6]).all(1)
     f = ((s[:, :3].astype(np.float32) - np.float32(lo)) / (np.float32(hi) - np.float32(lo)) * np.float32(res))
     idx = np.clip(np.floor(f).astype(int), 0, res - 1)
     cid = (idx[:, 2] * res + idx[:, 1]) * res + idx[:, 0]
     out = {}
     for c in cells:
-        m = cid == c
+        m = (cid == c) & use
         uv = s[m, 3:5]
+        wt = s[m, 5]
         dens = np.zeros(m.sum())
         for j in range(pi.shape[1]):
             if pi[c, j] <= 0:
@@ -65,7 +68,7 @@ def cell_ll(samples, lo, hi, res, pi, mu, cov, cells):
             d = uv - mu[c, j]
             q = (cc * d[:, 0] ** 2 - 2 * b * d[:, 0] * d[:, 1] + a * d[:, 1] ** 2) / det
             dens += pi[c, j] * np.exp(-0.5 * q) / (2 * np.pi * math.sqrt(det))
-        out[c] = float(np.mean(np.log(dens)))
+        out[c] = float(np.sum(wt * np.log(dens)) / np.sum(wt))
     return out
 
 

@@ -213,8 +213,8 @@ def test_determinism(mpg):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("bucketing,waves", [(1, 4), (1, 1), (0, 2)])
-def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves):
+@pytest.mark.parametrize("bucketing,waves,refill", [(1, 4, 0), (1, 1, 0), (0, 2, 0), (1, 4, 1), (1, 2, 1)])
+def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves, refill):
     """The persistent batched form computes every chain with the same code as
     the plain form, only scheduled differently: outputs are identical."""
     import torch
@@ -225,7 +225,7 @@ def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves):
     prim, pos, st = GC.oracle_seeds(osc, ep)
     plain = run_gpu_walk(mpg, sc, ep, prim, pos, st)
     pers = run_gpu_walk(mpg, sc, ep, prim, pos, st, form=mpg.FORM_PERSISTENT, bucketing=bucketing,
-                        waves_per_group=waves)
+                        waves_per_group=waves, refill=refill)
     for k in ("status", "iters", "sol", "G", "kappa", "residual"):
         assert np.array_equal(plain[k], pers[k]), k
     ok = plain["status"] != mpg.BAD_INPUT
