@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size kernel against which "
                          "hardware byte counters are scaled)")
+    ap.add_argument("--guide-n", type=int, default=1 << 22,
+                    help="configurations of the guided-sampling / Bernoulli-trial leg (0 = skip)")
     ap.add_argument("--adjoint-n", type=int, default=1 << 20,
                     help="chains of the forward+adjoint leg on the differentiation workload (0 = skip)")
     return ap.parse_args()
@@ -73,12 +75,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+TUNED_KNOBS = ("bucketing", "refill", "waves_per_group", "stack_depth")
+
+
 def load_tuned(path, workload):
+    """The autotuned knobs for a workload (the tuner's timing table stays in
+    the file)."""
     try:
         with open(path) as fh:
-            return json.load(fh).get(workload, {})
+            entry = json.load(fh).get(workload, {})
     except (OSError, ValueError):
         return {}
+    return {k: entry[k] for k in TUNED_KNOBS if k in entry}
 
 
 def cpu_model():
@@ -155,6 +163,60 @@ def graph_leg(M, prm, step, args, N):
     return {"ms_per_step": 1e3 * wall, "gpu_ms_per_step": e0.elapsed_time(e1) / steps, "graph_replays": steps}
 
 
+def guide_leg(M, W, args):
+    """The guided-sampling workload: 256^2 water height field, 2^20 training
+    configurations (p_0 seeds -> walk -> 64 Bernoulli trials -> sample
+    records) fit by weighted EM into the 32^3 x 8 guide, then 2^22 guided
+    configurations (alpha = 0.5) walked and each converged chain's 1/p
+    estimated with up to 64 trials.  Timed with HIP events per phase."""
+    import torch
+    sc = W.water_scene()
+    scene = M.Scene(sc)
+    # persistent form: length buckets, lane refill (walks and trials)
+    prm = M.walk_params(sc.scale, max_len=1, form=M.FORM_PERSISTENT, bucketing=1, refill=1)
+    stream = torch.cuda.current_stream()
+    tr = M.Endpoints(W.water_endpoints(1 << 20, stream=W.STREAM_TRAINING))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    ws = M.Workspace(max(tr.N, args.guide_n))
+    gd = M.Guide(W.WATER_GRID_LO, W.WATER_GRID_HI, res=32, scale=sc.scale)
+    for rep in range(2):  # the first pass warms up
+        ev[0].record(stream)
+        p, q, st = M.sample_seeds(scene, tr, prm, alpha=1.0, ws=ws)
+        p, q, outs = M.manifold_walk_batch(scene, prm, tr, p, q, st, out_prim=p, out_pos=q, ws=ws)
+        ev[1].record(stream)
+        trials, ip, _ = M.estimate_inv_prob(scene, prm, tr, p, q, outs["status"], max_trials=64, alpha=1.0, ws=ws)
+        ev[2].record(stream)
+        samples = M.make_guide_samples(tr, q, outs, ip)
+        M.fit_guide(scene, samples, gd, ws)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+    train = {"walk_ms": ev[0].elapsed_time(ev[1]), "trials_ms": ev[1].elapsed_time(ev[2]),
+             "fit_guide_ms": ev[2].elapsed_time(ev[3]), "samples": tr.N,
+             "trial_walks": int(trials.sum())}
+    ep = M.Endpoints(W.water_endpoints(args.guide_n))
+    prim, pos = M.empty_chains(ep.N)
+    outs = M.walk_outputs(ep.N)
+    res = None
+    for rep in range(2):
+        ev[4].record(stream)
+        p, q, st = M.sample_seeds(scene, ep, prm, alpha=0.5, guide=gd, out=(prim, pos), ws=ws)
+        M.manifold_walk_batch(scene, prm, ep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+        ev[5].record(stream)
+        trials, ip, trunc = M.estimate_inv_prob(scene, prm, ep, prim, pos, outs["status"], max_trials=64, alpha=0.5,
+                                                guide=gd, ws=ws)
+        ev[6].record(stream)
+        torch.cuda.synchronize()
+        conv = int((outs["status"] == M.CONVERGED).sum())
+        tw = int(trials.sum())
+        walk_ms, trial_ms = ev[4].elapsed_time(ev[5]), ev[5].elapsed_time(ev[6])
+        res = {"chains": ep.N, "converged": conv, "seeds_walk_ms": walk_ms, "trials_ms": trial_ms,
+               "trial_walks": tw, "truncated": int(trunc.sum()),
+               "converged_walks_per_s": conv / (walk_ms / 1e3),
+               "trial_walks_per_s": tw / (trial_ms / 1e3),
+               "walks_per_s_including_trials": (ep.N + tw) / ((walk_ms + trial_ms) / 1e3)}
+    return {"workload": "water_caustic", "training": train, "guided": res}
+
+
 def adjoint_leg(M, W, args, tuned_all, cone):
     """Forward walk + IFT adjoint on the differentiation workload: 2^20 chains
     of length 2..4 through the slab stack, loss sum(r . x + g G) with fixed
@@ -166,7 +228,7 @@ def adjoint_leg(M, W, args, tuned_all, cone):
     scene = M.Scene(sc)
     dep = M.Endpoints(ep)
     kw = dict(cone_cos=cone, max_len=4, defer_fp64=1, form=M.FORM_PERSISTENT)
-    for k in ("bucketing", "waves_per_group", "stack_depth", "refill"):
+    for k in TUNED_KNOBS:
         if k in tuned_all:
             kw[k] = int(tuned_all[k])
     prm = M.walk_params(sc.scale, **kw)
@@ -181,7 +243,7 @@ def adjoint_leg(M, W, args, tuned_all, cone):
     stream = torch.cuda.current_stream()
 
     def step():
-        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
         M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
         M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
 
@@ -249,7 +311,7 @@ def main():
         kw = dict(cone_cos=cone, max_len=MAX_LEN[name], defer_fp64=1,
                   form=M.FORM_PERSISTENT if form == "persistent" else M.FORM_PLAIN)
         if form == "persistent":
-            for k in ("bucketing", "waves_per_group", "stack_depth", "refill"):
+            for k in TUNED_KNOBS:
                 if k in tuned:
                     kw[k] = int(tuned[k])
         return M.walk_params(sc.scale, **kw)
@@ -260,7 +322,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(prm):
-        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
         M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
         M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
         return st
@@ -275,7 +337,7 @@ def main():
         for k in range(steps):
             e = ev[k]
             e[0].record(stream)
-            p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+            p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
             e[1].record(stream)
             M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
             e[2].record(stream)
@@ -320,6 +382,8 @@ def main():
         forms[main_form + "+graph"] = graph_leg(M, params(main_form), step, args, N)
     if args.adjoint_n > 0:
         forms["+adjoint"] = adjoint_leg(M, W, args, tuned_all=load_tuned(args.tuned, "slab_adjoint"), cone=cone)
+    if args.guide_n > 0:
+        forms["guided+trials"] = guide_leg(M, W, args)
 
     # untimed counting pass: algorithmic work of one walk launch
     prm_c = params("plain")

@@ -176,7 +176,8 @@ typedef struct {
   float fp64_graze_cos;      /* ... or when a vertex scatters with |cos| below this (0.02) */
   float cone_cos;            /* MPG_P0_DIRECTION: cosine of the cone half-angle about n_D */
   int32_t form;              /* MPG_FORM_PLAIN or MPG_FORM_PERSISTENT */
-  int32_t bucketing;         /* persistent form: sort chains by length first (1) or not (0) */
+  int32_t bucketing;         /* persistent form: group chains by length (1), by length and then by the
+                                spatial cell of x_D on a 32^3 Morton-ordered grid (2), or not at all (0) */
   int32_t waves_per_group;   /* wavefronts per workgroup (1, 2, 4) */
   int32_t stack_depth;       /* LDS traversal stack entries per lane (>= BVH depth + 1; 0 = automatic) */
   int32_t refill;            /* persistent form with bucketing: each lane takes a new chain as soon as its own
@@ -232,10 +233,14 @@ mpg_status mpg_guide_download(const mpg_guide* g, int32_t* valid, float* pi, flo
  * guide's target object; then w_D = normalize(p - x_D), x_1 = r(x_D, w_D)
  * and x_2..x_n by Eq. (deduction).  Random numbers: Philox4x64-10 with key
  * (philox_seed, 0) and counter (chain, trial, attempt, 0).  Writes prim/pos
- * for vertices 0..n-1 and d_status (0 or MPG_SEED_INVALID / MPG_BAD_INPUT). */
+ * for vertices 0..n-1 and d_status (0 or MPG_SEED_INVALID / MPG_BAD_INPUT).
+ * With params->form == MPG_FORM_PERSISTENT and bucketing on, the chains are
+ * grouped by length (and spatial cell) in the workspace ws (capacity >= N)
+ * and drawn by one persistent kernel per length; the seeds are identical to
+ * the plain launch's (ws may be NULL for the plain form). */
 mpg_status sample_seeds(const mpg_scene* scene, const mpg_guide* guide, const mpg_walk_params* params,
                         const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, float alpha,
-                        mpg_chains* out, int8_t* d_status, void* hip_stream);
+                        mpg_chains* out, int8_t* d_status, mpg_workspace* ws, void* hip_stream);
 
 /* Manifold walks (Sec. 3): Newton's method on the generalized half-vector
  * constraints with a block-tridiagonal Jacobian, reprojection by ray casting,
@@ -271,7 +276,11 @@ mpg_status mpg_walk_count(const mpg_scene* scene, const mpg_walk_params* params,
  * reaches the target again (same objects, every vertex within match_rel L);
  * K = that trial count, or max_trials when none matched (d_truncated = 1).
  * d_inv_prob = mean_r K_r / P(n) with P(n) = 1 (n is given), d_trials =
- * sum_r K_r.  Other targets get 0.  d_truncated may be NULL. */
+ * sum_r K_r.  Other targets get 0.  d_truncated may be NULL.  With
+ * params->form == MPG_FORM_PERSISTENT and bucketing on, the targets are
+ * grouped by length in ws (capacity >= N) and every lane of one persistent
+ * kernel per length takes the next target as soon as its trials end; the
+ * results equal the plain launch's (ws may be NULL for the plain form). */
 mpg_status estimate_inv_prob(const mpg_scene* scene, const mpg_guide* guide, const mpg_walk_params* params,
                              const mpg_endpoints* ep, const mpg_chains* target, const int8_t* d_target_status,
                              int32_t max_trials, int32_t repeats, uint64_t philox_seed, float alpha,

@@ -86,6 +86,7 @@ def lib():
         L.mpg_version.restype = C.c_char_p
         L.mpg_scene_create.argtypes = [C.POINTER(mpg_scene_desc), C.POINTER(P)]
         L.mpg_scene_destroy.argtypes = [P]
+        L.mpg_scene_set_params.argtypes = [P, P, I32, P]
         L.mpg_scene_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
         L.mpg_walk_params_default.argtypes = [F32, C.POINTER(mpg_walk_params)]
         L.mpg_workspace_create.argtypes = [I32, C.POINTER(P)]
@@ -95,7 +96,7 @@ def lib():
         L.mpg_guide_upload.argtypes = [P, P, P, P, P]
         L.mpg_guide_download.argtypes = [P, P, P, P, P, P]
         L.sample_seeds.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.c_uint64,
-                                   C.c_uint32, F32, C.POINTER(mpg_chains), P, P]
+                                   C.c_uint32, F32, C.POINTER(mpg_chains), P, P, P]
         L.manifold_walk_batch.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                           C.POINTER(mpg_chains), P, C.POINTER(mpg_chains), C.POINTER(mpg_walk_out),
                                           P, P]
@@ -112,7 +113,7 @@ def lib():
         for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
                      "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
-                     "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples"]:
+                     "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples", "mpg_scene_set_params"]:
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -296,13 +297,15 @@ def empty_chains(N, device="cuda"):
 # ---------------------------------------------------------------------------
 
 def sample_seeds(scene: Scene, ep: Endpoints, params: mpg_walk_params, seed=0, trial=0, alpha=0.5,
-                 guide: Optional[Guide] = None, out=None):
+                 guide: Optional[Guide] = None, out=None, ws: Optional[Workspace] = None, status=None):
+    """Seed chains; the persistent form (params.form) needs a workspace."""
     torch = _torch()
     prim, pos = out if out is not None else empty_chains(ep.N, ep.xD.device)
-    st = torch.zeros(ep.N, dtype=torch.int8, device=ep.xD.device)
+    st = torch.zeros(ep.N, dtype=torch.int8, device=ep.xD.device) if status is None else status
     ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
     _check(lib().sample_seeds(scene.h, guide.h if guide else None, C.byref(params), C.byref(ep.c()), int(seed),
-                              int(trial), float(alpha), C.byref(ch), st.data_ptr(), _stream()), "sample_seeds")
+                              int(trial), float(alpha), C.byref(ch), st.data_ptr(), ws.h if ws else None,
+                              _stream()), "sample_seeds")
     return prim, pos, st
 
 

@@ -1,6 +1,7 @@
 """Autotuner for the persistent batched walk.
 
-Sweeps the knobs of the persistent form -- length bucketing on / off, lane
+Sweeps the knobs of the persistent form -- bucketing (none, by length, by
+length and spatial cell), lane
 refill on / off, waves per workgroup (1, 2, 4) and the LDS BVH stack depth
 (the scene's minimum and larger) -- timing one manifold_walk_batch launch with HIP events on the
 caller's batch, and returns the fastest setting.  Every candidate produces the
@@ -27,7 +28,7 @@ from . import (FORM_PERSISTENT, Endpoints, MPGError, Scene, Workspace, empty_cha
 
 def candidates(min_depth: int):
     depths = sorted({min_depth, min_depth + 4, 2 * min_depth})
-    for bucketing, refill, waves, depth in itertools.product((1, 0), (1, 0), (1, 2, 4), depths):
+    for bucketing, refill, waves, depth in itertools.product((2, 1, 0), (1, 0), (1, 2, 4), depths):
         if waves * depth * 64 * 4 > 64 * 1024 or (refill and not bucketing):
             continue
         yield dict(bucketing=bucketing, refill=refill, waves_per_group=waves, stack_depth=depth)
@@ -39,8 +40,8 @@ def tune(scene: Scene, ep: Endpoints, base_kw: dict, reps: int = 3, log=None):
     N = ep.N
     min_depth = scene.stats()["max_depth"] + 1
     prm0 = walk_params(scene.scale, form=FORM_PERSISTENT, **base_kw)
-    seeds = sample_seeds(scene, ep, prm0)
     ws = Workspace(N)
+    seeds = sample_seeds(scene, ep, prm0, ws=ws)
     prim, pos = empty_chains(N)
     outs = walk_outputs(N)
     stream = torch.cuda.current_stream()

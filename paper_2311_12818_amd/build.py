@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpg.so")
 SOURCES = ["mpg_lib.hip", "mpg_persistent.hip", "mpg_guide.hip", "mpg_adjoint.hip", "mpg_params.hip",
-           "mpg_scene.cpp"]
+           "mpg_count.hip", "mpg_trials.hip", "mpg_scene.cpp"]
 HEADERS = ["mpg_device.h", "mpg_internal.h", "mpg_walk.h", "mpg_scene.h"]
 DEPS = SOURCES + HEADERS
 

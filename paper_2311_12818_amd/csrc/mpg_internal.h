@@ -19,10 +19,15 @@ using namespace mpg;
 
 // errors: a thread-local message for mpg_last_error()
 mpg_status fail(mpg_status code, const std::string& msg);
+// On a HIP error the runtime's per-thread error state is cleared before
+// returning, so that the failure is reported once, through the status code.
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess) return fail(MPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    if (e_ != hipSuccess) {                                                                  \
+      (void)hipGetLastError();                                                               \
+      return fail(MPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    }                                                                                        \
   } while (0)
 
 // ---------------------------------------------------------------------------
@@ -47,10 +52,16 @@ struct mpg_scene {
   uint32_t* zmax_bits = nullptr;
 };
 
+// persistent form: counter words per workspace, spatial cells per length
+#define MPG_WS_COUNTERS 128
+#define MPG_CELL_RES 32
+#define MPG_CELLS (MPG_CELL_RES * MPG_CELL_RES * MPG_CELL_RES)
+
 struct mpg_workspace {
   int32_t cap = 0;
   int32_t* perm = nullptr;     // [cap] chain order for the persistent form
-  int32_t* counters = nullptr; // [64] histogram / offsets / queue heads
+  int32_t* counters = nullptr; // [MPG_WS_COUNTERS] histogram / offsets / queue heads / batch box
+  int32_t* cells = nullptr;    // [2 * 8 * MPG_CELLS] spatial-cell counts and cursors
   int32_t* aux = nullptr;      // [cap] scratch (sample cell ids, sorted indices)
   std::vector<void*> allocs;
 };
@@ -132,13 +143,41 @@ struct WalkIO {
   float* resid;
 };
 
+// Counter words of the persistent forms (workspace counters): per-length
+// histogram, 64-padded bucket offsets, scatter cursors, queue heads (walk,
+// finish, seeds, trials), batch bounding box.
+enum : int {
+  CTR_HIST = 0, CTR_OFF = 16, CTR_CUR = 32, CTR_HEAD = 48, CTR_HEAD2 = 56, CTR_BOX = 64, CTR_HEAD3 = 72,
+  CTR_HEAD4 = 80
+};
+
+// Pull the next 64-slot batch of a queue; wave-uniform result.
+__device__ __forceinline__ int next_batch(int* head) {
+  int base = 0;
+  if ((threadIdx.x & 63) == 0) base = atomicAdd(head, 64);
+  return __shfl(base, 0, 64);
+}
+
+// persistent-form helpers (mpg_persistent.hip): resident workgroups of a
+// kernel across the device, length buckets of precomputed classes (1..8, 0 =
+// none) in ws->perm and ws->counters, fork / join of the four side streams
+int resident_blocks(const void* fn, int threads, size_t lds);
+mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream_t stream);
+mpg_status side_fork(hipStream_t stream, hipStream_t side[4]);
+mpg_status side_join(hipStream_t stream);
+
 // host-side checks shared by every entry point
+mpg_status walk_io(const mpg_chains* chains, const mpg_walk_out* wout, WalkIO* io);
 mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams* w, int* waves);
 mpg_status check_endpoints(const mpg_endpoints* e, EpView* v);
 
 // persistent form (its own translation unit)
 mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
                            int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream);
+mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P, int waves,
+                            int bucketing, const EpView& E, uint64_t seed, uint32_t trial, float alpha,
+                            int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,
+                            hipStream_t stream);
 // plain FP32 finish pass over a whole batch (used by the unbucketed persistent form)
 mpg_status launch_finish_plain(const mpg_scene* s, const WalkParams& P, const EpView& E, const WalkIO& io,
                                int max_len, int threads, size_t lds, hipStream_t stream);

@@ -258,7 +258,8 @@ extern "C" mpg_status mpg_workspace_create(int32_t max_chains, mpg_workspace** o
   w->cap = max_chains;
   hipError_t e;
   if ((e = dalloc(w->allocs, &w->perm, (size_t)max_chains + 8 * 64)) != hipSuccess ||
-      (e = dalloc(w->allocs, &w->counters, 64)) != hipSuccess ||
+      (e = dalloc(w->allocs, &w->counters, MPG_WS_COUNTERS)) != hipSuccess ||
+      (e = dalloc(w->allocs, &w->cells, (size_t)2 * KMAX * MPG_CELLS)) != hipSuccess ||
       (e = dalloc(w->allocs, &w->aux, (size_t)max_chains + 64)) != hipSuccess) {
     free_all(w->allocs);
     delete w;
@@ -276,25 +277,6 @@ extern "C" void mpg_workspace_destroy(mpg_workspace* w) {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-template <int N, class STK>
-__device__ __forceinline__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
-                         uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
-                         STK& stk) {
-  int prim[N];
-  f3 pos[N];
-  int r = sample_seed<N>(S, G, P, E.type[c], E.obj1[c], ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), seed,
-                         (uint64_t)c, trial, alpha, prim, pos, stk);
-  st[c] = (int8_t)r;
-  const size_t NN = E.N;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    prim_out[i * NN + c] = r == 0 ? prim[i] : PRIM_NONE;
-    pos_out[(0 * KMAX + i) * NN + c] = r == 0 ? pos[i].x : 0.f;
-    pos_out[(1 * KMAX + i) * NN + c] = r == 0 ? pos[i].y : 0.f;
-    pos_out[(2 * KMAX + i) * NN + c] = r == 0 ? pos[i].z : 0.f;
-  }
-}
-
 __global__ void k_sample_seeds(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E, uint64_t seed,
                                uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,34 +319,6 @@ __global__ void __launch_bounds__(256) k_finish_pass(DevScene S, WalkParams P, E
 }
 
 // FP64 pass over the chains the walk left as ST_NEEDS_FP64.
-template <int N, class STK>
-__device__ __forceinline__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
-                         STK& stk) {
-  const size_t NN = E.N;
-  int prim[N];
-  f3 x[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    prim[i] = io.prim_out[i * NN + c];
-    x[i] = {io.pos_out[(0 * KMAX + i) * NN + c], io.pos_out[(1 * KMAX + i) * NN + c],
-            io.pos_out[(2 * KMAX + i) * NN + c]};
-  }
-  WalkOut R;
-  R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
-  finish_fp64<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
-  io.status[c] = (int8_t)R.status;
-  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
-  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
-  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
-  if (io.resid) io.resid[c] = R.resid;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    io.pos_out[(0 * KMAX + i) * NN + c] = x[i].x;
-    io.pos_out[(1 * KMAX + i) * NN + c] = x[i].y;
-    io.pos_out[(2 * KMAX + i) * NN + c] = x[i].z;
-  }
-}
-
 template <int NMAX>
 __global__ void __launch_bounds__(256) k_fp64_pass(DevScene S, WalkParams P, EpView E, WalkIO io) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,58 +343,7 @@ __global__ void __launch_bounds__(256) k_fp64_pass(DevScene S, WalkParams P, EpV
 // vertex evaluations, FP64 vertex evaluations); the tallies are reduced into
 // counts[0..6], counts[7] = chains.  Used untimed to obtain the algorithmic
 // work of a launch.
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_walk_count(DevScene S, WalkParams P, EpView E, WalkIO io,
-                                                    unsigned long long* counts) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  Stack base = lane_stack(P.depth);
-  CountStack stk{base.base, base.depth, 0, 0, 0, 0, 0, 0, 0};
-  if (c < E.N) walk_dispatch<NMAX>(S, P, E, io, c, stk);
-  if (c < E.N) finish_dispatch<NMAX>(S, P, E, io, c, stk);
-  if (c < E.N && io.status[c] == ST_NEEDS_FP64) {
-    int n = E.len[c];
-    switch (n) {
-      case 1: fp64_one<1>(S, P, E, io, c, stk); break;
-      case 2: if (NMAX >= 2) fp64_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
-      case 3: if (NMAX >= 3) fp64_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
-      case 4: if (NMAX >= 4) fp64_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
-      case 5: if (NMAX >= 5) fp64_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
-      case 6: if (NMAX >= 6) fp64_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
-      case 7: if (NMAX >= 7) fp64_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
-      default: if (NMAX >= 8) fp64_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
-    }
-  }
-  if (c < E.N) {
-    atomicAdd(&counts[0], (unsigned long long)stk.nbox);
-    atomicAdd(&counts[1], (unsigned long long)stk.ntri);
-    atomicAdd(&counts[2], (unsigned long long)stk.nsph);
-    atomicAdd(&counts[3], (unsigned long long)stk.nray);
-    atomicAdd(&counts[4], (unsigned long long)stk.nvc);
-    atomicAdd(&counts[5], (unsigned long long)stk.nvj);
-    atomicAdd(&counts[6], (unsigned long long)stk.nvj64);
-    atomicAdd(&counts[7], 1ULL);
-  }
-}
-
-__global__ void k_zero_u64(unsigned long long* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ULL;
-}
-
 typedef void (*walk_kernel_t)(DevScene, WalkParams, EpView, WalkIO);
-typedef void (*count_kernel_t)(DevScene, WalkParams, EpView, WalkIO, unsigned long long*);
-static count_kernel_t count_kernel(int nmax) {
-  switch (nmax) {
-    case 1: return k_walk_count<1>;
-    case 2: return k_walk_count<2>;
-    case 3: return k_walk_count<3>;
-    case 4: return k_walk_count<4>;
-    case 5: return k_walk_count<5>;
-    case 6: return k_walk_count<6>;
-    case 7: return k_walk_count<7>;
-    default: return k_walk_count<8>;
-  }
-}
 static walk_kernel_t plain_kernel(int nmax) {
   switch (nmax) {
     case 1: return k_walk_plain<1>;
@@ -487,89 +390,6 @@ mpg_status launch_finish_plain(const mpg_scene* s, const WalkParams& P, const Ep
 }
 
 // ---------------------------------------------------------------------------
-// Bernoulli trials (Sec. 5.8)
-// ---------------------------------------------------------------------------
-struct InvIO {
-  const int32_t* tprim;
-  const float* tpos;
-  const int8_t* tstatus;
-  int32_t* trials;
-  float* inv_prob;
-  uint8_t* truncated;
-  int max_trials, repeats;
-  uint64_t seed;
-  float alpha;
-};
-
-template <int N, class STK>
-__device__ __forceinline__ void inv_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E,
-                        const InvIO& io, int c, STK& stk) {
-  const size_t NN = E.N;
-  f3 tx[N];
-  int tobj[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    tx[i] = {io.tpos[(0 * KMAX + i) * NN + c], io.tpos[(1 * KMAX + i) * NN + c], io.tpos[(2 * KMAX + i) * NN + c]};
-    tobj[i] = prim_obj(S, io.tprim[i * NN + c]);
-  }
-  f3 xD = ld_pt(E.xD, E.N, c), nD = ld_pt(E.nD, E.N, c), xL = ld_pt(E.xL, E.N, c);
-  int type = E.type[c], obj1 = E.obj1[c];
-  int total = 0;
-  bool trunc = false;
-  for (int r = 0; r < io.repeats; ++r) {
-    int K = io.max_trials;
-    bool found = false;
-    for (int k = 1; k <= io.max_trials && !found; ++k) {
-      uint64_t trial = 1 + (uint64_t)r * io.max_trials + (uint64_t)(k - 1);
-      int prim[N];
-      f3 x[N];
-      if (sample_seed<N>(S, G, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, prim, x, stk) != 0)
-        continue;
-      int it;
-      int ws = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
-      if (ws != ST_CONVERGED && ws != ST_NEEDS_FP64) continue;
-      bool m = true;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        f3 d = x[i] - tx[i];
-        m = m && prim_obj(S, prim[i]) == tobj[i] && dot(d, d) <= P.match2;
-      }
-      if (m) { K = k; found = true; }
-    }
-    if (!found) trunc = true;
-    total += K;
-  }
-  io.trials[c] = total;
-  io.inv_prob[c] = (float)total / (float)io.repeats;
-  if (io.truncated) io.truncated[c] = trunc ? 1 : 0;
-}
-
-__global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E,
-                                                  InvIO io) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  Stack stk = lane_stack(P.depth);
-  if (c >= E.N) return;
-  int n = E.len[c];
-  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > KMAX || io.repeats < 1 || io.max_trials < 1) {
-    io.trials[c] = 0;
-    io.inv_prob[c] = 0.f;
-    if (io.truncated) io.truncated[c] = 0;
-    return;
-  }
-  const DevGuide* g = has_guide ? &G : nullptr;
-  switch (n) {
-    case 1: inv_one<1>(S, g, P, E, io, c, stk); break;
-    case 2: inv_one<2>(S, g, P, E, io, c, stk); break;
-    case 3: inv_one<3>(S, g, P, E, io, c, stk); break;
-    case 4: inv_one<4>(S, g, P, E, io, c, stk); break;
-    case 5: inv_one<5>(S, g, P, E, io, c, stk); break;
-    case 6: inv_one<6>(S, g, P, E, io, c, stk); break;
-    case 7: inv_one<7>(S, g, P, E, io, c, stk); break;
-    default: inv_one<8>(S, g, P, E, io, c, stk); break;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // host entry points
 // ---------------------------------------------------------------------------
 mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams* w, int* waves) {
@@ -578,6 +398,7 @@ mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams
   if (!(p->scale > 0.0f)) return fail(MPG_ERR_INVALID_ARG, "scale must be positive");
   if (!(p->tol_vertex >= 0.0f) || !(p->tol_residual >= 0.0f) || !(p->tmin_rel >= 0.0f) || !(p->match_rel >= 0.0f))
     return fail(MPG_ERR_INVALID_ARG, "negative tolerance");
+  if (p->bucketing < 0 || p->bucketing > 2) return fail(MPG_ERR_INVALID_ARG, "bucketing must be 0, 1 or 2");
   if (p->waves_per_group != 1 && p->waves_per_group != 2 && p->waves_per_group != 4)
     return fail(MPG_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4");
   int need = s->max_depth + 1;
@@ -613,7 +434,7 @@ mpg_status check_endpoints(const mpg_endpoints* e, EpView* v) {
 
 extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const mpg_walk_params* p,
                                    const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, float alpha,
-                                   mpg_chains* out, int8_t* d_status, void* stream) {
+                                   mpg_chains* out, int8_t* d_status, mpg_workspace* ws, void* stream) {
   if (!s) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: NULL scene");
   WalkParams P;
   int waves;
@@ -627,6 +448,11 @@ extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const
   DevGuide G;
   std::memset(&G, 0, sizeof(G));
   if (g) G = g->dev();
+  if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
+    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: workspace too small");
+    return seeds_persistent(s, G, g ? 1 : 0, P, waves, p->bucketing, E, philox_seed, trial, alpha, out->d_prim,
+                            out->d_pos, d_status, ws, (hipStream_t)stream);
+  }
   int threads = 64 * waves;
   size_t lds = (size_t)waves * P.depth * 64 * 4;
   hipLaunchKernelGGL(k_sample_seeds, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
@@ -676,7 +502,7 @@ extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_par
   return MPG_OK;
 }
 
-static mpg_status walk_io(const mpg_chains* chains, const mpg_walk_out* wout, WalkIO* io) {
+mpg_status walk_io(const mpg_chains* chains, const mpg_walk_out* wout, WalkIO* io) {
   if (!chains || !chains->d_prim || !chains->d_pos || !wout || !wout->d_status)
     return fail(MPG_ERR_INVALID_ARG, "NULL chains or status");
   io->seed_prim = chains->d_prim; io->seed_pos = chains->d_pos; io->seed_status = nullptr;
@@ -702,65 +528,6 @@ extern "C" mpg_status manifold_walk_fp64(const mpg_scene* s, const mpg_walk_para
   size_t lds = (size_t)waves * P.depth * 64 * 4;
   hipLaunchKernelGGL(fp64_kernel(p->max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds,
                      (hipStream_t)stream, s->dev, P, E, io);
-  HIP_TRY(hipGetLastError());
-  return MPG_OK;
-}
-
-extern "C" mpg_status mpg_walk_count(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
-                                     const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
-                                     const mpg_walk_out* wout, uint64_t* d_counts, void* stream) {
-  if (!s) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL scene");
-  WalkParams P;
-  int waves;
-  EpView E;
-  WalkIO io;
-  mpg_status st;
-  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
-  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
-  if (!d_counts) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL counts");
-  if ((st = walk_io(out, wout, &io)) != MPG_OK) return st;
-  if (!seeds || !seeds->d_prim || !seeds->d_pos) return fail(MPG_ERR_INVALID_ARG, "mpg_walk_count: NULL seeds");
-  io.seed_prim = seeds->d_prim; io.seed_pos = seeds->d_pos; io.seed_status = d_seed_status;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)stream, (unsigned long long*)d_counts, 8);
-  HIP_TRY(hipGetLastError());
-  if (E.N == 0) return MPG_OK;
-  int threads = 64 * waves;
-  size_t lds = (size_t)waves * P.depth * 64 * 4;
-  hipLaunchKernelGGL(count_kernel(p->max_len), dim3((E.N + threads - 1) / threads), dim3(threads), lds,
-                     (hipStream_t)stream, s->dev, P, E, io, (unsigned long long*)d_counts);
-  HIP_TRY(hipGetLastError());
-  return MPG_OK;
-}
-
-extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, const mpg_walk_params* p,
-                                        const mpg_endpoints* ep, const mpg_chains* target,
-                                        const int8_t* d_target_status, int32_t max_trials, int32_t repeats,
-                                        uint64_t philox_seed, float alpha, int32_t* d_trials, float* d_inv_prob,
-                                        uint8_t* d_truncated, mpg_workspace* ws, void* stream) {
-  (void)ws;
-  if (!s) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: NULL scene");
-  WalkParams P;
-  int waves;
-  EpView E;
-  mpg_status st;
-  if ((st = check_params(s, p, &P, &waves)) != MPG_OK) return st;
-  if ((st = check_endpoints(ep, &E)) != MPG_OK) return st;
-  if (E.N == 0) return MPG_OK;
-  if (!target || !target->d_prim || !target->d_pos || !d_target_status || !d_trials || !d_inv_prob)
-    return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: NULL argument");
-  if (max_trials < 0 || repeats < 0) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: negative trial count");
-  if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: alpha outside [0, 1]");
-  DevGuide G;
-  std::memset(&G, 0, sizeof(G));
-  if (g) G = g->dev();
-  InvIO io;
-  io.tprim = target->d_prim; io.tpos = target->d_pos; io.tstatus = d_target_status;
-  io.trials = d_trials; io.inv_prob = d_inv_prob; io.truncated = d_truncated;
-  io.max_trials = max_trials; io.repeats = repeats; io.seed = philox_seed; io.alpha = alpha;
-  int threads = 64 * waves;
-  size_t lds = (size_t)waves * P.depth * 64 * 4;
-  hipLaunchKernelGGL(k_inv_prob, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
-                     s->dev, G, g ? 1 : 0, P, E, io);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }

@@ -8,24 +8,25 @@
 // 2. k_bucket_scan: one wave turns the histogram into bucket offsets, each
 //    bucket padded to a multiple of 64 so that a wavefront's batch never
 //    straddles two lengths; padding slots get -1; queue heads are zeroed.
-// 3. k_bucket_scatter: block-aggregated slot reservation, perm[] = chain ids.
+// 3. k_bucket_scatter: block-aggregated slot reservation, perm[] = chain ids
+//    (bucketing = 2: ordered by spatial cell inside each bucket, see below).
 // 4. One persistent kernel per length N (its own register budget), sized to
 //    the machine's occupancy; each wavefront pulls 64-slot batches from its
 //    bucket's atomic queue until the bucket drains.
 // Without bucketing a single persistent kernel pulls batches of 64
 // consecutive chains of mixed length.  All launches are graph-capture safe.
 
-enum : int { CTR_HIST = 0, CTR_OFF = 16, CTR_CUR = 32, CTR_HEAD = 48, CTR_HEAD2 = 56 };
 
-__global__ void __launch_bounds__(256) k_bucket_hist(EpView E, WalkIO io, int max_len, int* ctr, int8_t* cls) {
+__global__ void __launch_bounds__(256) k_bucket_hist(EpView E, WalkIO io, int max_len, int check_xl, int* ctr,
+                                                     int8_t* cls) {
   __shared__ int h[KMAX + 1];
   if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
   __syncthreads();
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < E.N) {
     int n = E.len[c];
-    bool ok = n >= 1 && n <= max_len && finite3(ld_pt(E.xD, E.N, c)) && finite3(ld_pt(E.xL, E.N, c)) &&
-              finite3(ld_pt(E.nD, E.N, c));
+    bool ok = n >= 1 && n <= max_len && finite3(ld_pt(E.xD, E.N, c)) &&
+              (!check_xl || finite3(ld_pt(E.xL, E.N, c))) && finite3(ld_pt(E.nD, E.N, c));
     int b = ok ? n : 0;
     cls[c] = (int8_t)b;
     if (b == 0) {
@@ -44,7 +45,125 @@ __global__ void __launch_bounds__(256) k_bucket_hist(EpView E, WalkIO io, int ma
 }
 
 __global__ void k_bucket_zero(int* ctr) {
-  if (threadIdx.x < 64) ctr[threadIdx.x] = 0;
+  if (threadIdx.x < MPG_WS_COUNTERS) ctr[threadIdx.x] = 0;
+}
+
+// Histogram of precomputed classes (1..8; 0 = no slot).
+__global__ void __launch_bounds__(256) k_class_hist(int N, const int8_t* cls, int* ctr) {
+  __shared__ int h[KMAX + 1];
+  if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
+  __syncthreads();
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N && cls[c] > 0) atomicAdd(&h[(int)cls[c]], 1);
+  __syncthreads();
+  if (threadIdx.x >= 1 && threadIdx.x <= KMAX && h[threadIdx.x]) atomicAdd(&ctr[CTR_HIST + threadIdx.x], h[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Spatial order inside each length bucket (bucketing = 2): chains are binned
+// by the Morton index of x_D on a 32^3 grid over the batch's bounding box, so
+// that the chains a wavefront takes together start close to each other and
+// trace nearly the same BVH nodes.  Counting sort with atomic cursors (the
+// order inside a cell is arbitrary; every chain's result is independent of
+// it).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ordered_key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ordered_value(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 5 bits -> every third bit
+  v &= 31u;
+  v = (v | (v << 8)) & 0x0000f00fu;
+  v = (v | (v << 4)) & 0x000c30c3u;
+  v = (v | (v << 2)) & 0x00249249u;
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_cells_zero(int* cells, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cells[i] = 0;
+}
+
+// bounding box of the valid shading points: per-wave reduction, then one
+// atomic max per wave and bound (minima as max of the complemented keys)
+__global__ void __launch_bounds__(256) k_box_reduce(EpView E, const int8_t* cls, int* ctr) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t hi[3] = {0u, 0u, 0u}, lo[3] = {0u, 0u, 0u};
+  if (c < E.N && cls[c] > 0) {
+    f3 x = ld_pt(E.xD, E.N, c);
+    float v[3] = {x.x, x.y, x.z};
+    for (int a = 0; a < 3; ++a) { hi[a] = ordered_key(v[a]); lo[a] = ~ordered_key(v[a]); }
+  }
+  for (int a = 0; a < 3; ++a) {
+    for (int o = 32; o > 0; o >>= 1) {
+      hi[a] = max(hi[a], (uint32_t)__shfl_xor((int)hi[a], o, 64));
+      lo[a] = max(lo[a], (uint32_t)__shfl_xor((int)lo[a], o, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      if (hi[a]) atomicMax((unsigned int*)&ctr[CTR_BOX + a], hi[a]);
+      if (lo[a]) atomicMax((unsigned int*)&ctr[CTR_BOX + 3 + a], lo[a]);
+    }
+  }
+}
+
+__device__ __forceinline__ int cell_bin(const EpView& E, const int* ctr, int c, int len) {
+  f3 x = ld_pt(E.xD, E.N, c);
+  float v[3] = {x.x, x.y, x.z};
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    float lo = ordered_value(~(uint32_t)ctr[CTR_BOX + 3 + a]), hi = ordered_value((uint32_t)ctr[CTR_BOX + a]);
+    float ext = hi - lo;
+    float u = ext > 0.0f ? (v[a] - lo) / ext : 0.0f;
+    int k = (int)(u * (float)MPG_CELL_RES);
+    q[a] = (uint32_t)min(max(k, 0), MPG_CELL_RES - 1);
+  }
+  int morton = (int)(spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2));
+  return (len - 1) * MPG_CELLS + morton;
+}
+
+__global__ void __launch_bounds__(256) k_cell_hist(EpView E, const int8_t* cls, const int* ctr, int* hist) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= E.N || cls[c] <= 0) return;
+  atomicAdd(&hist[cell_bin(E, ctr, c, cls[c])], 1);
+}
+
+// exclusive scan of every length's cell counts, offset by the (64-padded)
+// start of the length's bucket: cursors for the scatter.  One block of 1024.
+__global__ void __launch_bounds__(1024) k_cell_scan(const int* ctr, const int* hist, int* cursor) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  constexpr int PER = MPG_CELLS / 1024;
+  for (int len = 1; len <= KMAX; ++len) {
+    const int* h = hist + (len - 1) * MPG_CELLS;
+    int local = 0;
+    for (int i = 0; i < PER; ++i) local += h[t * PER + i];
+    part[t] = local;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int v = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = ctr[CTR_OFF + len] + part[t] - local;
+    for (int i = 0; i < PER; ++i) {
+      cursor[(len - 1) * MPG_CELLS + t * PER + i] = run;
+      run += h[t * PER + i];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cell_scatter(EpView E, const int8_t* cls, const int* ctr, int* cursor,
+                                                      int* perm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= E.N || cls[c] <= 0) return;
+  int slot = atomicAdd(&cursor[cell_bin(E, ctr, c, cls[c])], 1);
+  perm[slot] = c;
 }
 
 __global__ void k_bucket_scan(int* ctr, int* perm) {
@@ -87,12 +206,6 @@ __global__ void __launch_bounds__(256) k_bucket_scatter(int N, const int8_t* cls
   if (b > 0) perm[ctr[CTR_OFF + b] + base[b] + local] = c;
 }
 
-// Pull the next 64-slot batch of a queue; wave-uniform result.
-__device__ __forceinline__ int next_batch(int* head) {
-  int base = 0;
-  if ((threadIdx.x & 63) == 0) base = atomicAdd(head, 64);
-  return __shfl(base, 0, 64);
-}
 
 template <int N>
 __global__ void __launch_bounds__(256) k_walk_persist(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr,
@@ -185,6 +298,26 @@ __global__ void __launch_bounds__(256) k_finish_persist(DevScene S, WalkParams P
   }
 }
 
+// Seed sampling of one length bucket (same queue scheme, third head): every
+// chain of a bucket traces the same number of deduction rays.
+template <int N>
+__global__ void __launch_bounds__(256) k_seeds_persist(DevScene S, DevGuide G, int has_guide, WalkParams P,
+                                                       EpView E, uint64_t seed, uint64_t trial, float alpha,
+                                                       int32_t* prim_out, float* pos_out, int8_t* st, int* ctr,
+                                                       const int* perm) {
+  Stack stk = lane_stack(P.depth);
+  const int start = ctr[CTR_OFF + N];
+  const int end = ctr[CTR_OFF + N + 1];
+  const int lane = threadIdx.x & 63;
+  const DevGuide* g = has_guide ? &G : nullptr;
+  for (;;) {
+    int base = next_batch(&ctr[CTR_HEAD3 + N - 1]);
+    if (start + base >= end) break;
+    int c = perm[start + base + lane];
+    if (c >= 0) seed_one<N>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk);
+  }
+}
+
 template <int NMAX>
 __global__ void __launch_bounds__(256) k_walk_persist_mixed(DevScene S, WalkParams P, EpView E, WalkIO io,
                                                             int* ctr) {
@@ -237,6 +370,20 @@ static persist_kernel_t refill_kernel(int n) {
     default: return k_walk_refill<8>;
   }
 }
+typedef void (*seeds_kernel_t)(DevScene, DevGuide, int, WalkParams, EpView, uint64_t, uint64_t, float, int32_t*,
+                               float*, int8_t*, int*, const int*);
+static seeds_kernel_t seeds_kernel(int n) {
+  switch (n) {
+    case 1: return k_seeds_persist<1>;
+    case 2: return k_seeds_persist<2>;
+    case 3: return k_seeds_persist<3>;
+    case 4: return k_seeds_persist<4>;
+    case 5: return k_seeds_persist<5>;
+    case 6: return k_seeds_persist<6>;
+    case 7: return k_seeds_persist<7>;
+    default: return k_seeds_persist<8>;
+  }
+}
 static mixed_kernel_t mixed_kernel(int nmax) {
   switch (nmax) {
     case 1: return k_walk_persist_mixed<1>;
@@ -251,7 +398,7 @@ static mixed_kernel_t mixed_kernel(int nmax) {
 }
 
 // Resident workgroups of a kernel across the device (persistent grid size).
-static int resident_blocks(const void* fn, int threads, size_t lds) {
+int resident_blocks(const void* fn, int threads, size_t lds) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -289,13 +436,114 @@ static mpg_status side_streams(SideStreams** out) {
   return MPG_OK;
 }
 
+// Length buckets (and, for bucketing = 2, spatial order inside them) of a
+// batch in ws->perm; chains that fail the input checks get MPG_BAD_INPUT in
+// io.status and no slot.
+static mpg_status bucket_chains(int bucketing, int max_len, int check_xl, const EpView& E, const WalkIO& io,
+                                mpg_workspace* ws, hipStream_t stream) {
+  const int blocks = (E.N + 255) / 256;
+  int* ctr = ws->counters;
+  int8_t* cls = (int8_t*)ws->aux;
+  hipLaunchKernelGGL(k_bucket_hist, dim3(blocks), dim3(256), 0, stream, E, io, max_len, check_xl, ctr, cls);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
+  HIP_TRY(hipGetLastError());
+  if (bucketing == 2) {
+    int* hist = ws->cells;
+    int* cursor = ws->cells + KMAX * MPG_CELLS;
+    hipLaunchKernelGGL(k_cells_zero, dim3(256), dim3(256), 0, stream, hist, KMAX * MPG_CELLS);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_box_reduce, dim3(blocks), dim3(256), 0, stream, E, (const int8_t*)cls, ctr);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_hist, dim3(blocks), dim3(256), 0, stream, E, (const int8_t*)cls, (const int*)ctr, hist);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, stream, (const int*)ctr, (const int*)hist, cursor);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks), dim3(256), 0, stream, E, (const int8_t*)cls, (const int*)ctr,
+                       cursor, ws->perm);
+  } else {
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, E.N, (const int8_t*)cls, ctr, ws->perm);
+  }
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P, int waves,
+                            int bucketing, const EpView& E, uint64_t seed, uint32_t trial, float alpha,
+                            int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,
+                            hipStream_t stream) {
+  const int threads = 64 * waves;
+  const size_t lds = (size_t)waves * P.depth * 64 * 4;
+  int* ctr = ws->counters;
+  hipLaunchKernelGGL(k_bucket_zero, dim3(1), dim3(MPG_WS_COUNTERS), 0, stream, ctr);
+  HIP_TRY(hipGetLastError());
+  WalkIO io;
+  std::memset(&io, 0, sizeof(io));
+  io.status = status;
+  mpg_status bst = bucket_chains(bucketing, KMAX, 0, E, io, ws, stream);
+  if (bst != MPG_OK) return bst;
+  SideStreams* ss;
+  mpg_status st = side_streams(&ss);
+  if (st != MPG_OK) return st;
+  HIP_TRY(hipEventRecord(ss->fork, stream));
+  for (int k = 0; k < 4; ++k) HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
+  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) & 3) {
+    seeds_kernel_t k = seeds_kernel(n);
+    int grid = resident_blocks((const void*)k, threads, lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, G, has_guide, P, E, seed,
+                       (uint64_t)trial, alpha, prim_out, pos_out, status, ctr, (const int*)ws->perm);
+    HIP_TRY(hipGetLastError());
+  }
+  for (int k = 0; k < 4; ++k) {
+    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
+    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
+  }
+  return MPG_OK;
+}
+
+mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream_t stream) {
+  const int blocks = (N + 255) / 256;
+  int* ctr = ws->counters;
+  hipLaunchKernelGGL(k_bucket_zero, dim3(1), dim3(MPG_WS_COUNTERS), 0, stream, ctr);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_class_hist, dim3(blocks), dim3(256), 0, stream, N, cls, ctr);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, N, cls, ctr, ws->perm);
+  HIP_TRY(hipGetLastError());
+  return MPG_OK;
+}
+
+mpg_status side_fork(hipStream_t stream, hipStream_t side[4]) {
+  SideStreams* ss;
+  mpg_status st = side_streams(&ss);
+  if (st != MPG_OK) return st;
+  HIP_TRY(hipEventRecord(ss->fork, stream));
+  for (int k = 0; k < 4; ++k) {
+    HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
+    side[k] = ss->s[k];
+  }
+  return MPG_OK;
+}
+
+mpg_status side_join(hipStream_t stream) {
+  SideStreams* ss;
+  mpg_status st = side_streams(&ss);
+  if (st != MPG_OK) return st;
+  for (int k = 0; k < 4; ++k) {
+    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
+    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
+  }
+  return MPG_OK;
+}
+
 mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
                            int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream) {
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
-  const int blocks = (E.N + 255) / 256;
   int* ctr = ws->counters;
-  hipLaunchKernelGGL(k_bucket_zero, dim3(1), dim3(64), 0, stream, ctr);
+  hipLaunchKernelGGL(k_bucket_zero, dim3(1), dim3(MPG_WS_COUNTERS), 0, stream, ctr);
   HIP_TRY(hipGetLastError());
   if (!bucketing) {
     mixed_kernel_t k = mixed_kernel(max_len);
@@ -304,13 +552,8 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
     HIP_TRY(hipGetLastError());
     return launch_finish_plain(s, P, E, io, max_len, threads, lds, stream);
   }
-  int8_t* cls = (int8_t*)ws->aux;
-  hipLaunchKernelGGL(k_bucket_hist, dim3(blocks), dim3(256), 0, stream, E, io, max_len, ctr, cls);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, E.N, (const int8_t*)cls, ctr, ws->perm);
-  HIP_TRY(hipGetLastError());
+  mpg_status bst = bucket_chains(bucketing, max_len, 1, E, io, ws, stream);
+  if (bst != MPG_OK) return bst;
   SideStreams* ss;
   mpg_status st = side_streams(&ss);
   if (st != MPG_OK) return st;

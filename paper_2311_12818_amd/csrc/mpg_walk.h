@@ -131,3 +131,52 @@ __device__ __forceinline__ void finish_dispatch(const DevScene& S, const WalkPar
   }
 }
 
+// FP64 pass over one chain the walk left as ST_NEEDS_FP64.
+template <int N, class STK>
+__device__ __forceinline__ void fp64_one(const DevScene& S, const WalkParams& P, const EpView& E, const WalkIO& io, int c,
+                         STK& stk) {
+  const size_t NN = E.N;
+  int prim[N];
+  f3 x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim[i] = io.prim_out[i * NN + c];
+    x[i] = {io.pos_out[(0 * KMAX + i) * NN + c], io.pos_out[(1 * KMAX + i) * NN + c],
+            io.pos_out[(2 * KMAX + i) * NN + c]};
+  }
+  WalkOut R;
+  R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
+  finish_fp64<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
+  io.status[c] = (int8_t)R.status;
+  if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
+  if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
+  if (io.kappa) io.kappa[c] = R.status == ST_CONVERGED ? R.kappa : 0.f;
+  if (io.resid) io.resid[c] = R.resid;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    io.pos_out[(0 * KMAX + i) * NN + c] = x[i].x;
+    io.pos_out[(1 * KMAX + i) * NN + c] = x[i].y;
+    io.pos_out[(2 * KMAX + i) * NN + c] = x[i].z;
+  }
+}
+
+// Seed chain of configuration c (sample_seed), stored as the walk reads it.
+template <int N, class STK>
+__device__ __forceinline__ void seed_one(const DevScene& S, const DevGuide* G, const WalkParams& P, const EpView& E, int c,
+                         uint64_t seed, uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st,
+                         STK& stk) {
+  int prim[N];
+  f3 pos[N];
+  int r = sample_seed<N>(S, G, P, E.type[c], E.obj1[c], ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), seed,
+                         (uint64_t)c, trial, alpha, prim, pos, stk);
+  st[c] = (int8_t)r;
+  const size_t NN = E.N;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prim_out[i * NN + c] = r == 0 ? prim[i] : PRIM_NONE;
+    pos_out[(0 * KMAX + i) * NN + c] = r == 0 ? pos[i].x : 0.f;
+    pos_out[(1 * KMAX + i) * NN + c] = r == 0 ? pos[i].y : 0.f;
+    pos_out[(2 * KMAX + i) * NN + c] = r == 0 ? pos[i].z : 0.f;
+  }
+}
+

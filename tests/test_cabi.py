@@ -43,4 +43,4 @@ def test_host_side_errors_without_gpu():
     assert L.mpg_walk_params_default(2.0, ctypes.byref(p)) == 0
     assert p.max_iter == 20 and abs(p.tol_vertex - 1e-4) < 1e-9 and p.max_len == 8
     assert L.manifold_walk_batch(None, ctypes.byref(p), None, None, None, None, None, None, None) == -1
-    assert L.sample_seeds(None, None, None, None, 0, 0, 0.5, None, None, None) == -1
+    assert L.sample_seeds(None, None, None, None, 0, 0, 0.5, None, None, None, None) == -1

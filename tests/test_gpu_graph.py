@@ -36,7 +36,7 @@ def test_captured_step_replays_match_eager(mpg):
     seed_status = torch.zeros(n, dtype=torch.int8, device="cuda")
 
     def step():
-        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
         seed_status.copy_(st)
         M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
         M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
@@ -63,7 +63,7 @@ def test_captured_step_replays_match_eager(mpg):
             v.fill_(-1) if v.dtype != torch.float32 else v.fill_(float("nan"))
         prim.fill_(-7)
         pos.fill_(float("nan"))
-        p2, q2, s2 = M.sample_seeds(scene, dep2, prm)
+        p2, q2, s2 = M.sample_seeds(scene, dep2, prm, ws=ws)
         M.manifold_walk_batch(scene, prm, dep2, p2, q2, s2, ws=ws)   # reuses (clobbers) the workspace
         torch.cuda.synchronize()
         g.replay()

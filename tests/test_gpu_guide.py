@@ -231,3 +231,29 @@ def test_water_pipeline_guided_beats_p0(mpg):
     print(dict(rates=rates, valid_cells=int(g["valid"].sum())), flush=True)
     assert g["valid"].sum() > 1000
     assert rates[0.5] > rates[1.0] + 0.05
+
+
+def test_persistent_trials_match_plain(mpg):
+    """Bernoulli trials through the persistent lane-refill kernels give the
+    plain launch's counts bit for bit (same seeds, walks and matches)."""
+    import torch
+    sc = W.water_scene()
+    scene = mpg.Scene(sc)
+    ep = W.water_endpoints(20000 + 11, seed=6)
+    ep.length[5] = 0                      # not a target: zero output on both paths
+    dep = mpg.Endpoints(ep)
+    plain = mpg.walk_params(sc.scale, max_len=1)
+    pers = mpg.walk_params(sc.scale, max_len=1, form=mpg.FORM_PERSISTENT, bucketing=1, refill=1)
+    ws = mpg.Workspace(ep.n)
+    prim, pos, st = mpg.sample_seeds(scene, dep, plain, alpha=1.0)
+    prim, pos, outs = mpg.manifold_walk_batch(scene, plain, dep, prim, pos, st, out_prim=prim, out_pos=pos)
+    a = mpg.estimate_inv_prob(scene, plain, dep, prim, pos, outs["status"], max_trials=16, repeats=2, alpha=1.0)
+    b = mpg.estimate_inv_prob(scene, pers, dep, prim, pos, outs["status"], max_trials=16, repeats=2, alpha=1.0,
+                              ws=ws)
+    torch.cuda.synchronize()
+    conv = GC.to_np(outs["status"]) == mpg.CONVERGED
+    assert conv.sum() > 1000
+    for x, y in zip(a, b):
+        assert np.array_equal(GC.to_np(x), GC.to_np(y))
+    assert (GC.to_np(b[0])[~conv] == 0).all() and (GC.to_np(b[0])[conv] >= 2).all()
+

@@ -213,7 +213,8 @@ def test_determinism(mpg):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("bucketing,waves,refill", [(1, 4, 0), (1, 1, 0), (0, 2, 0), (1, 4, 1), (1, 2, 1)])
+@pytest.mark.parametrize("bucketing,waves,refill", [(1, 4, 0), (1, 1, 0), (0, 2, 0), (1, 4, 1), (1, 2, 1), (2, 1, 1),
+                                                   (2, 4, 0)])
 def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves, refill):
     """The persistent batched form computes every chain with the same code as
     the plain form, only scheduled differently: outputs are identical."""
@@ -277,3 +278,29 @@ def test_counting_walk_matches_and_counts(mpg):
     assert counts["chains"] == ep.n
     assert counts["rays"] > ep.n and counts["box_tests"] > counts["rays"] and counts["tri_tests"] > 0
     assert counts["vertex_jacobian_evals"] > 0 and counts["vertex_residual_evals"] > 0
+
+
+@pytest.mark.parametrize("bucketing", [1, 2])
+def test_persistent_seeds_match_plain_seeds(mpg, bucketing):
+    """Seeds drawn by the persistent per-length kernels equal the plain
+    launch's bit for bit (same routine, same Philox counters)."""
+    import torch
+    sc = W.slab_stack_scene()
+    ep = W.slab_uneven_endpoints(30000 + 5, seed=4)
+    ep.length[3] = 0            # invalid length -> bad input on both paths
+    scene = mpg.Scene(sc)
+    dep = mpg.Endpoints(ep)
+    plain = mpg.walk_params(sc.scale, cone_cos=GC.cone_cos())
+    pers = mpg.walk_params(sc.scale, cone_cos=GC.cone_cos(), form=mpg.FORM_PERSISTENT, bucketing=bucketing)
+    ws = mpg.Workspace(ep.n)
+    a = mpg.sample_seeds(scene, dep, plain, seed=9, trial=2)
+    b = mpg.sample_seeds(scene, dep, pers, seed=9, trial=2, ws=ws)
+    torch.cuda.synchronize()
+    sa, sb = GC.to_np(a[2]), GC.to_np(b[2])
+    assert np.array_equal(sa, sb) and sa[3] == mpg.BAD_INPUT
+    ok = sa == 0
+    assert ok.mean() > 0.5
+    used = (np.arange(8)[:, None] < ep.length[None, :]) & ok[None, :]
+    assert np.array_equal(GC.to_np(a[0])[used], GC.to_np(b[0])[used])
+    assert np.array_equal(GC.to_np(a[1])[:, used], GC.to_np(b[1])[:, used])
+
