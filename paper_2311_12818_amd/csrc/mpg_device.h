@@ -155,7 +155,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
 // device scene
 // ---------------------------------------------------------------------------
 struct DevScene {
-  const float4* nodes;      // 4 x float4 per node: child boxes (L, R) + int4 (left, right, 0, 0)
+  const float4* nodes;      // 8 x float4 per 4-wide node: child boxes (SoA) + int4 child references + pad
   const float4* tri_v;      // 3 x float4 per triangle in BVH order; v0.w = primitive id (int bits)
   const int4* tri_idx;      // [n_tris] vertex ids (i0, i1, i2) and object
   const float4* vpos;       // [n_verts]
@@ -307,35 +307,59 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
   int ref = 0;
   for (;;) {
     if (ref >= 0) {
-      stk.box(2);
-      const float4* nd = S.nodes + 4 * (size_t)ref;
-      float4 a = nd[0], b = nd[1], c = nd[2];
-      int4 ch = *reinterpret_cast<const int4*>(nd + 3);
-      float lx0 = fmaf(a.x, inv.x, -oinv.x), lx1 = fmaf(a.w, inv.x, -oinv.x);
-      float ly0 = fmaf(a.y, inv.y, -oinv.y), ly1 = fmaf(b.x, inv.y, -oinv.y);
-      float lz0 = fmaf(a.z, inv.z, -oinv.z), lz1 = fmaf(b.y, inv.z, -oinv.z);
-      float rx0 = fmaf(b.z, inv.x, -oinv.x), rx1 = fmaf(c.y, inv.x, -oinv.x);
-      float ry0 = fmaf(b.w, inv.y, -oinv.y), ry1 = fmaf(c.z, inv.y, -oinv.y);
-      float rz0 = fmaf(c.x, inv.z, -oinv.z), rz1 = fmaf(c.w, inv.z, -oinv.z);
-      float tl0 = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fmaxf(fminf(lz0, lz1), tmin));
-      float tl1 = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fminf(fmaxf(lz0, lz1), h.t));
-      float tr0 = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fmaxf(fminf(rz0, rz1), tmin));
-      float tr1 = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fminf(fmaxf(rz0, rz1), h.t));
-      bool hl = tl0 <= tl1, hr = tr0 <= tr1;
-      if (hl && hr) {
-        int nearc = tl0 <= tr0 ? ch.x : ch.y;
-        int farc = tl0 <= tr0 ? ch.y : ch.x;
-        if (sp >= stk.depth) return false;
-        stk.base[sp * 64] = farc;
-        ++sp;
-        ref = nearc;
+      // 4-wide node: slab test of the four child boxes (SoA), then descend
+      // into the nearest hit child and push the others, farthest first
+      if (ref >= S.n_nodes) return false;
+      stk.box(4);
+      const float4* nd = S.nodes + 8 * (size_t)ref;
+      const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5];
+      const int4 ch = *reinterpret_cast<const int4*>(nd + 6);
+      float tn[4];
+      int cr[4];
+      {
+        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, lya[4] = {ly.x, ly.y, ly.z, ly.w};
+        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+        const float hya[4] = {hy.x, hy.y, hy.z, hy.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+        const int cha[4] = {ch.x, ch.y, ch.z, ch.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float x0 = fmaf(lxa[k], inv.x, -oinv.x), x1 = fmaf(hxa[k], inv.x, -oinv.x);
+          float y0 = fmaf(lya[k], inv.y, -oinv.y), y1 = fmaf(hya[k], inv.y, -oinv.y);
+          float z0 = fmaf(lza[k], inv.z, -oinv.z), z1 = fmaf(hza[k], inv.z, -oinv.z);
+          float t0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
+          float t1 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), h.t));
+          tn[k] = t0 <= t1 ? t0 : INFINITY;
+          cr[k] = cha[k];
+        }
+      }
+      // sort the four entry distances (misses at +infinity last)
+#define MPG_CSWAP(a, b)                                                     \
+  if (tn[b] < tn[a]) {                                                      \
+    float tt = tn[a]; tn[a] = tn[b]; tn[b] = tt;                            \
+    int rr = cr[a]; cr[a] = cr[b]; cr[b] = rr;                              \
+  }
+      MPG_CSWAP(0, 1) MPG_CSWAP(2, 3) MPG_CSWAP(0, 2) MPG_CSWAP(1, 3) MPG_CSWAP(1, 2)
+#undef MPG_CSWAP
+      if (tn[0] == INFINITY) {
+        if (sp == 0) break;
+        --sp;
+        ref = stk.base[sp * 64];
         continue;
       }
-      if (hl) { ref = ch.x; continue; }
-      if (hr) { ref = ch.y; continue; }
+#pragma unroll
+      for (int k = 3; k >= 1; --k) {
+        if (tn[k] != INFINITY) {
+          if (sp >= stk.depth) return false;
+          stk.base[sp * 64] = cr[k];
+          ++sp;
+        }
+      }
+      ref = cr[0];
+      continue;
     } else {
       int start = ref & 0xFFFFFF;
       int count = (ref >> 24) & 0x7F;
+      if (start + count > S.n_tris) return false;
       for (int k = start; k < start + count; ++k) {
         float4 v0 = S.tri_v[3 * (size_t)k], v1 = S.tri_v[3 * (size_t)k + 1], v2 = S.tri_v[3 * (size_t)k + 2];
         int prim = __float_as_int(v0.w);

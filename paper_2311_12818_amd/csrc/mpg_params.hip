@@ -80,16 +80,17 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-// BVH refit: one wavefront per node; each child box is the bounding box of
-// the triangles of its range, padded like the builder's (empty: unpadded)
-__global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* ranges, const float4* tri_v, float4* nodes,
+// BVH refit: one wavefront per 4-wide node; each child box is the bounding
+// box of the triangles of its range, padded like the builder's (an empty
+// child keeps its box at +infinity)
+__global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* ranges, const float4* tri_v, float* nodes,
                                                float pad) {
   int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (g >= n_nodes) return;
-  float b[12];
-  for (int q = 0; q < 2; ++q) {
-    int start = ranges[4 * (size_t)g + 2 * q], count = ranges[4 * (size_t)g + 2 * q + 1];
+  float* f = nodes + 32 * (size_t)g;
+  for (int q = 0; q < 4; ++q) {
+    int start = ranges[8 * (size_t)g + 2 * q], count = ranges[8 * (size_t)g + 2 * q + 1];
     float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
     for (int i = lane; i < 3 * count; i += 64) {
       float4 p = tri_v[3 * (size_t)start + i];
@@ -99,15 +100,20 @@ __global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* range
     for (int a = 0; a < 3; ++a) {
       lo[a] = wave_min(lo[a]);
       hi[a] = wave_max(hi[a]);
-      if (count > 0) { lo[a] -= pad; hi[a] += pad; }
-      b[6 * q + a] = lo[a];
-      b[6 * q + 3 + a] = hi[a];
+      if (count > 0) {
+        lo[a] -= pad;
+        hi[a] += pad;
+      } else {
+        lo[a] = INFINITY;
+        hi[a] = INFINITY;
+      }
     }
-  }
-  if (lane == 0) {
-    nodes[4 * (size_t)g + 0] = make_float4(b[0], b[1], b[2], b[3]);
-    nodes[4 * (size_t)g + 1] = make_float4(b[4], b[5], b[6], b[7]);
-    nodes[4 * (size_t)g + 2] = make_float4(b[8], b[9], b[10], b[11]);
+    if (lane == 0) {
+      for (int a = 0; a < 3; ++a) {
+        f[4 * a + q] = lo[a];
+        f[12 + 4 * a + q] = hi[a];
+      }
+    }
   }
 }
 
@@ -170,7 +176,7 @@ extern "C" mpg_status mpg_scene_set_params(mpg_scene* s, const float* d_theta, i
                        D.tri_idx, D.vpos, (float4*)D.tri_v);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_refit, dim3((s->n_nodes + 3) / 4), dim3(256), 0, stream, s->n_nodes, s->ranges, D.tri_v,
-                       (float4*)D.nodes, s->pad);
+                       (float*)D.nodes, s->pad);
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_area_cdf, dim3((s->n_objects + 1 + 63) / 64), dim3(64), 0, stream, s->n_objects + 1, D.cdf_range, D.cdf_prim, D.tri_idx,

@@ -124,60 +124,93 @@ int build_bvh(const float* verts, const int32_t* tris, int n_tris, float pad, st
     jobs.push_back({l, j.start, mid - j.start});
     jobs.push_back({l + 1, mid, j.start + j.count - mid});
   }
-  // emit GPU nodes: interior nodes only, each holding both child boxes
-  std::vector<int> gidx(tree.size(), -1);
-  int n_int = 0;
-  int depth = 1;
-  bool root_leaf = tree[0].left < 0;
-  if (root_leaf) {
-    n_int = 1;
-  } else {
-    for (size_t i = 0; i < tree.size(); ++i)
-      if (tree[i].left >= 0) { gidx[i] = n_int++; depth = std::max(depth, tree[i].depth); }
-  }
-  gpu_nodes.assign((size_t)n_int * 16, 0.0f);
-  ranges.assign((size_t)n_int * 4, 0);
-  auto ref_of = [&](int ti) -> int32_t {
-    const TreeNode& t = tree[ti];
-    if (t.left >= 0) return gidx[ti];
-    return (int32_t)(0x80000000u | ((uint32_t)t.count << 24) | (uint32_t)t.start);
+  // collapse the binary tree into 4-wide nodes: starting from a node's two
+  // children, the interior child with the largest box is replaced by its own
+  // two children until there are four or only leaves remain
+  struct Wide {
+    int child[4];  // tree indices, -1 = empty
+    int level;
   };
-  auto put = [&](int g, const Box& L, const Box& R, int32_t lref, int32_t rref) {
-    float* f = &gpu_nodes[(size_t)g * 16];
-    Box l = L, r = R;
-    for (int a = 0; a < 3; ++a) {
-      if (!l.empty()) { l.lo[a] -= pad; l.hi[a] += pad; }
-      if (!r.empty()) { r.lo[a] -= pad; r.hi[a] += pad; }
+  std::vector<Wide> wide;
+  std::vector<int> stack_tree, stack_level, stack_slot;
+  auto open_children = [&](int ti, int* out) {
+    int list[4];
+    int n = 0;
+    if (tree[ti].left < 0) {
+      list[n++] = ti;  // a leaf root: one leaf child
+    } else {
+      list[n++] = tree[ti].left;
+      list[n++] = tree[ti].right;
+      while (n < 4) {
+        int best = -1;
+        float area = -1.0f;
+        for (int k = 0; k < n; ++k)
+          if (tree[list[k]].left >= 0 && tree[list[k]].box.area() > area) { area = tree[list[k]].box.area(); best = k; }
+        if (best < 0) break;
+        int t = list[best];
+        list[best] = tree[t].left;
+        for (int k = n; k > best + 1; --k) list[k] = list[k - 1];
+        list[best + 1] = tree[t].right;
+        ++n;
+      }
     }
-    f[0] = l.lo[0]; f[1] = l.lo[1]; f[2] = l.lo[2]; f[3] = l.hi[0];
-    f[4] = l.hi[1]; f[5] = l.hi[2]; f[6] = r.lo[0]; f[7] = r.lo[1];
-    f[8] = r.lo[2]; f[9] = r.hi[0]; f[10] = r.hi[1]; f[11] = r.hi[2];
-    std::memcpy(&f[12], &lref, 4);
-    std::memcpy(&f[13], &rref, 4);
-    int32_t z = 0;
-    std::memcpy(&f[14], &z, 4);
-    std::memcpy(&f[15], &z, 4);
+    for (int k = 0; k < 4; ++k) out[k] = k < n ? list[k] : -1;
   };
-  if (root_leaf) {
-    Box empty;
-    int32_t lref = (int32_t)(0x80000000u | ((uint32_t)tree[0].count << 24) | (uint32_t)tree[0].start);
-    int32_t rref = (int32_t)0x80000000u;  // empty leaf
-    put(0, tree[0].box, empty, lref, rref);
-    ranges[0] = tree[0].start;
-    ranges[1] = tree[0].count;
-  } else {
-    for (size_t i = 0; i < tree.size(); ++i) {
-      if (tree[i].left < 0) continue;
-      put(gidx[i], tree[tree[i].left].box, tree[tree[i].right].box, ref_of(tree[i].left), ref_of(tree[i].right));
-      int32_t* r = &ranges[(size_t)gidx[i] * 4];
-      r[0] = tree[tree[i].left].start;
-      r[1] = tree[tree[i].left].count;
-      r[2] = tree[tree[i].right].start;
-      r[3] = tree[tree[i].right].count;
+  // depth-first emission, parents before children; pending (tree node, parent slot) pairs
+  struct Pending {
+    int tree, parent, slot, level;
+  };
+  std::vector<Pending> todo;
+  todo.push_back({0, -1, -1, 1});
+  std::vector<int32_t> child_ref;  // 4 per wide node, filled as children are emitted
+  int levels = 1;
+  while (!todo.empty()) {
+    Pending pd = todo.back();
+    todo.pop_back();
+    int w = (int)wide.size();
+    Wide nd;
+    open_children(pd.tree, nd.child);
+    nd.level = pd.level;
+    levels = std::max(levels, pd.level);
+    wide.push_back(nd);
+    child_ref.resize((size_t)(w + 1) * 4, (int32_t)0x80000000u);
+    if (pd.parent >= 0) child_ref[(size_t)pd.parent * 4 + pd.slot] = w;
+    for (int k = 3; k >= 0; --k) {
+      int c = nd.child[k];
+      if (c < 0) continue;
+      if (tree[c].left >= 0)
+        todo.push_back({c, w, k, pd.level + 1});
+      else
+        child_ref[(size_t)w * 4 + k] =
+            (int32_t)(0x80000000u | ((uint32_t)tree[c].count << 24) | (uint32_t)tree[c].start);
     }
   }
-  *max_depth = depth;
-  return n_int;
+  const int n_wide = (int)wide.size();
+  gpu_nodes.assign((size_t)n_wide * 32, 0.0f);
+  ranges.assign((size_t)n_wide * 8, 0);
+  for (int w = 0; w < n_wide; ++w) {
+    float* f = &gpu_nodes[(size_t)w * 32];
+    for (int k = 0; k < 4; ++k) {
+      int c = wide[w].child[k];
+      float lo[3], hi[3];
+      if (c < 0) {
+        for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = INFINITY; }  // never hit
+      } else {
+        for (int a = 0; a < 3; ++a) { lo[a] = tree[c].box.lo[a] - pad; hi[a] = tree[c].box.hi[a] + pad; }
+        ranges[(size_t)w * 8 + 2 * k] = tree[c].start;
+        ranges[(size_t)w * 8 + 2 * k + 1] = tree[c].count;
+      }
+      for (int a = 0; a < 3; ++a) {
+        f[4 * a + k] = lo[a];
+        f[12 + 4 * a + k] = hi[a];
+      }
+      int32_t ref = child_ref[(size_t)w * 4 + k];
+      std::memcpy(&f[24 + k], &ref, 4);
+    }
+  }
+  // near-first traversal pushes at most three children per level
+  *max_depth = 3 * levels;
+  return n_wide;
 }
 
 }  // namespace mpg_host
