@@ -254,7 +254,7 @@ def adjoint_leg(M, W, args, tuned_all, cone):
     def adj():
         gth.zero_()
         M.manifold_walk_adjoint(scene, prm, dep, prim, pos, outs["status"], rt, gt, grad_xD=gxD, grad_xL=gxL,
-                                grad_theta=gth)
+                                grad_theta=gth, ws=ws)
 
     for _ in range(max(1, args.warmup)):
         step()

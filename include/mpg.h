@@ -319,11 +319,14 @@ mpg_status make_guide_samples(const mpg_endpoints* ep, const mpg_chains* chains,
  * ids are out of range) get zero gradients and add nothing.  The chains must
  * be the converged output of manifold_walk_batch on the same scene and
  * endpoints; params->max_len bounds the lengths handled.  All buffers are
- * device memory owned by the caller; the call is asynchronous on hip_stream. */
+ * device memory owned by the caller; the call is asynchronous on hip_stream.
+ * With params->form == MPG_FORM_PERSISTENT and bucketing on, chains are
+ * grouped by length in ws (capacity >= N) and each length runs in its own
+ * persistent kernel (ws may be NULL for the plain form). */
 mpg_status manifold_walk_adjoint(const mpg_scene* scene, const mpg_walk_params* params, const mpg_endpoints* ep,
                                  const mpg_chains* converged, const int8_t* d_status, const float* d_grad_pos,
                                  const float* d_grad_G, float* d_grad_xD, float* d_grad_xL, float* d_grad_theta,
-                                 void* hip_stream);
+                                 mpg_workspace* ws, void* hip_stream);
 
 #ifdef __cplusplus
 }

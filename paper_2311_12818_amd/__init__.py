@@ -109,7 +109,7 @@ def lib():
         L.mpg_walk_count.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.POINTER(mpg_chains),
                                      P, C.POINTER(mpg_chains), C.POINTER(mpg_walk_out), P, P]
         L.manifold_walk_adjoint.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
-                                            C.POINTER(mpg_chains), P, P, P, P, P, P, P]
+                                            C.POINTER(mpg_chains), P, P, P, P, P, P, P, P]
         for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
                      "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
@@ -402,7 +402,7 @@ def fit_guide(scene: Scene, samples, guide: Guide, ws: Workspace):
 
 
 def manifold_walk_adjoint(scene: Scene, params: mpg_walk_params, ep: Endpoints, prim, pos, status, grad_pos=None,
-                          grad_G=None, grad_xD=None, grad_xL=None, grad_theta=None):
+                          grad_G=None, grad_xD=None, grad_xL=None, grad_theta=None, ws: Optional[Workspace] = None):
     torch = _torch()
     dev = ep.xD.device
     grad_xD = torch.zeros((3, ep.N), dtype=torch.float32, device=dev) if grad_xD is None else grad_xD
@@ -412,5 +412,6 @@ def manifold_walk_adjoint(scene: Scene, params: mpg_walk_params, ep: Endpoints, 
     ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
     _check(lib().manifold_walk_adjoint(scene.h, C.byref(params), C.byref(ep.c()), C.byref(ch), status.data_ptr(),
                                        _ptr(grad_pos), _ptr(grad_G), grad_xD.data_ptr(), grad_xL.data_ptr(),
-                                       grad_theta.data_ptr(), _stream()), "manifold_walk_adjoint")
+                                       grad_theta.data_ptr(), ws.h if ws else None, _stream()),
+           "manifold_walk_adjoint")
     return grad_xD, grad_xL, grad_theta

@@ -12,8 +12,8 @@ place (mpg_scene_set_params: vertices, normals, BVH refit, area tables).
 """
 from __future__ import annotations
 
-from . import (MPGError, Endpoints, Scene, empty_chains, manifold_walk_adjoint, manifold_walk_batch,
-               manifold_walk_fp64, walk_outputs)
+from . import (FORM_PERSISTENT, MPGError, Endpoints, Scene, Workspace, empty_chains, manifold_walk_adjoint,
+               manifold_walk_batch, manifold_walk_fp64, walk_outputs)
 
 
 class WalkProblem:
@@ -24,6 +24,8 @@ class WalkProblem:
 
     def __init__(self, scene: Scene, params, nD, length, types, obj1, seed_prim, seed_pos, seed_status=None):
         self._scene = scene
+        # the persistent form needs a workspace for the walk and the adjoint
+        self.ws = Workspace(int(length.shape[0])) if params.form == FORM_PERSISTENT else None
         self.params = params
         self.nD, self.length, self.types, self.obj1 = nD, length, types, obj1
         self.seed_prim, self.seed_pos, self.seed_status = seed_prim, seed_pos, seed_status
@@ -60,7 +62,7 @@ def _function():
             prim, pos = empty_chains(ep.N, xD.device)
             outs = walk_outputs(ep.N, xD.device)
             manifold_walk_batch(scene, prm, ep, problem.seed_prim, problem.seed_pos, problem.seed_status,
-                                out_prim=prim, out_pos=pos, outs=outs)
+                                out_prim=prim, out_pos=pos, outs=outs, ws=problem.ws)
             manifold_walk_fp64(scene, prm, ep, prim, pos, outs)
             ctx.problem, ctx.ep = problem, ep
             ctx.theta_value = theta.detach().clone()
@@ -81,7 +83,7 @@ def _function():
             dev = pos.device
             gth = torch.zeros(max(1, scene.n_params), dtype=torch.float32, device=dev)
             gxD, gxL, gth = manifold_walk_adjoint(scene, ctx.problem.params, ep, prim, pos, status, gp, gG,
-                                                  grad_theta=gth)
+                                                  grad_theta=gth, ws=ctx.problem.ws)
             shape, dtype = ctx.theta_meta
             g_theta = gth[:scene.n_params].to(dtype).reshape(shape) if ctx.needs_input_grad[2] else None
             return (gxD.to(ctx.xD_dtype) if ctx.needs_input_grad[0] else None,

@@ -257,9 +257,27 @@ __device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k ==
 
 // Returns false only on stack overflow (the library sizes stacks so that it
 // cannot happen).  h.prim == PRIM_NONE when nothing was hit.
+// Watertight ray/triangle test on the sheared frame (rx, ry, rz) of the ray:
+// the hit distance, or +infinity.
+__device__ __forceinline__ float tri_test(f3 rx, f3 ry, f3 rz, f3 o, float4 v0, float4 v1, float4 v2) {
+  f3 A = ld3(v0) - o, B = ld3(v1) - o, C = ld3(v2) - o;
+  float Ax = dot(rx, A), Ay = dot(ry, A), Bx = dot(rx, B), By = dot(ry, B), Cx = dot(rx, C), Cy = dot(ry, C);
+  float U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
+  if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return INFINITY;
+  float det = U + V + W;
+  if (det == 0.f) return INFINITY;
+  float T = U * dot(rz, A) + V * dot(rz, B) + W * dot(rz, C);
+  return T / det;
+}
+
+// First hit of the ray o + t d, t in (tmin, tmax), over the specular
+// surfaces, skipping primitive excl.  cand (a triangle id, optional) is tested
+// before the traversal: its hit, when there is one, bounds the traversal,
+// which then only looks for closer hits; ties go to the smaller primitive id
+// either way, so the result does not depend on cand.
 template <class STK>
 __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& h, STK& stk,
-                      float tmax = INFINITY) {
+                      float tmax = INFINITY, int cand = PRIM_NONE) {
   h.t = tmax;
   h.prim = PRIM_NONE;
   stk.ray();
@@ -303,6 +321,12 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
             1.0f / (fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y)),
             1.0f / (fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z))};
   f3 oinv = {o.x * inv.x, o.y * inv.y, o.z * inv.z};
+  if (cand >= 0 && cand < S.n_tris && cand != excl) {
+    stk.tri();
+    int4 id = S.tri_idx[cand];
+    float t = tri_test(rx, ry, rz, o, S.vpos[id.x], S.vpos[id.y], S.vpos[id.z]);
+    if (t > tmin) take(h, cand, t);
+  }
   int sp = 0;
   int ref = 0;
   for (;;) {
@@ -365,14 +389,7 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
         int prim = __float_as_int(v0.w);
         if (prim == excl) continue;
         stk.tri();
-        f3 A = ld3(v0) - o, B = ld3(v1) - o, C = ld3(v2) - o;
-        float Ax = dot(rx, A), Ay = dot(ry, A), Bx = dot(rx, B), By = dot(ry, B), Cx = dot(rx, C), Cy = dot(ry, C);
-        float U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
-        if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) continue;
-        float det = U + V + W;
-        if (det == 0.f) continue;
-        float T = U * dot(rz, A) + V * dot(rz, B) + W * dot(rz, C);
-        float t = T / det;
+        float t = tri_test(rx, ry, rz, o, v0, v1, v2);
         if (t > tmin) take(h, prim, t);
       }
     }
@@ -705,8 +722,8 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
 // (x_0 = x_D) toward the displaced vertex i; the first hit must lie on vertex
 // i's object.
 template <int N, class STK>
-__device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x, const f3* dl, float beta,
-                                          const int* obj, float tmin, STK& stk, f3* xn, int* pn) {
+__device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x, const int* prim, const f3* dl,
+                                          float beta, const int* obj, float tmin, STK& stk, f3* xn, int* pn) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     f3 o = i == 0 ? xD : xn[i > 0 ? i - 1 : 0];
@@ -720,10 +737,11 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
     d = d * il;
     // The surface is expected near the target: search [tmin, bound] first;
     // the closest hit there is the closest overall.  Only a miss needs the
-    // unbounded traversal.
+    // unbounded traversal.  The vertex's current triangle is tested first
+    // (the moved point usually stays on it), which tightens the bound.
     float bound = 1.5f * l2 * il + 2.0f * norm(step) + 4.0f * tmin;
     Hit h;
-    if (!trace(S, o, d, excl, tmin, h, stk, bound)) return false;
+    if (!trace(S, o, d, excl, tmin, h, stk, bound, prim[i])) return false;
     if (h.prim == PRIM_NONE && !trace(S, o, d, excl, tmin, h, stk)) return false;
     if (h.prim == PRIM_NONE || prim_obj(S, h.prim) != obj[i]) return false;
     xn[i] = fmav(d, h.t, o);
@@ -784,7 +802,7 @@ __device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P,
   int pn[N];
   const bool small = w.step2 <= P.tol_step2;
   const float bt = small ? 1.0f : w.beta;
-  if (!reproject<N>(S, xD, w.x, w.dl, bt, w.obj, P.tmin, stk, xn, pn)) {
+  if (!reproject<N>(S, xD, w.x, w.prim, w.dl, bt, w.obj, P.tmin, stk, xn, pn)) {
     w.beta = 0.5f * bt;
     return -1;
   }

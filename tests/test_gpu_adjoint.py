@@ -271,3 +271,30 @@ def test_autograd_function_matches_central_differences(mpg):
             an = float((grad * u).double().sum())
             print(dict(which=which, kept=int(keep.sum()), fd=fd, adjoint=an), flush=True)
             assert an == pytest.approx(fd, rel=1e-2, abs=0.05)
+
+
+def test_persistent_adjoint_matches_plain(mpg):
+    """Length-bucketed persistent adjoint kernels: the same per-chain
+    gradients as the plain launch (x_D, x_L bit for bit; theta up to the
+    order of the atomic float additions)."""
+    import torch
+    M = mpg
+    sc = W.slab_stack_scene()
+    ep = W.slab_adjoint_endpoints(12000 + 7, seed=9)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    plain = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), max_len=4)
+    pers = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), max_len=4, form=M.FORM_PERSISTENT, bucketing=1)
+    ws = M.Workspace(ep.n)
+    p, q, st = M.sample_seeds(scene, dep, plain)
+    prim, pos, outs = M.manifold_walk_batch(scene, plain, dep, p, q, st)
+    r, g = W.loss_weights(ep.n, seed=10)
+    rt, gt = torch.as_tensor(r).cuda(), torch.as_tensor(g).cuda()
+    a = M.manifold_walk_adjoint(scene, plain, dep, prim, pos, outs["status"], rt, gt)
+    b = M.manifold_walk_adjoint(scene, pers, dep, prim, pos, outs["status"], rt, gt, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(GC.to_np(a[0]), GC.to_np(b[0])) and np.array_equal(GC.to_np(a[1]), GC.to_np(b[1]))
+    ta, tb = GC.to_np(a[2]).astype(np.float64), GC.to_np(b[2]).astype(np.float64)
+    assert np.all(np.abs(ta - tb) <= 1e-4 * np.abs(ta).max() + 1e-6)
+    assert (GC.to_np(outs["status"]) == M.CONVERGED).sum() > 5000
+
