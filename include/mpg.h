@@ -177,7 +177,9 @@ typedef struct {
   float cone_cos;            /* MPG_P0_DIRECTION: cosine of the cone half-angle about n_D */
   int32_t form;              /* MPG_FORM_PLAIN or MPG_FORM_PERSISTENT */
   int32_t bucketing;         /* persistent form: group chains by length (1), by length and then by the
-                                spatial cell of x_D on a 32^3 Morton-ordered grid (2), or not at all (0) */
+                                spatial cell of x_D on a 32^3 Morton-ordered grid (2), as 2 with each
+                                bucket split into 8 spatial ranges, one per XCD, for the lane-refill
+                                walk (3), or not at all (0) */
   int32_t waves_per_group;   /* wavefronts per workgroup (1, 2, 4) */
   int32_t stack_depth;       /* LDS traversal stack entries per lane (>= BVH depth + 1; 0 = automatic) */
   int32_t refill;            /* persistent form with bucketing: each lane takes a new chain as soon as its own

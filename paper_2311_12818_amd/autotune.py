@@ -28,8 +28,8 @@ from . import (FORM_PERSISTENT, Endpoints, MPGError, Scene, Workspace, empty_cha
 
 def candidates(min_depth: int):
     depths = sorted({min_depth, min_depth + 4, 2 * min_depth})
-    for bucketing, refill, waves, depth in itertools.product((2, 1, 0), (1, 0), (1, 2, 4), depths):
-        if waves * depth * 64 * 4 > 64 * 1024 or (refill and not bucketing):
+    for bucketing, refill, waves, depth in itertools.product((3, 2, 1, 0), (1, 0), (1, 2, 4), depths):
+        if waves * depth * 64 * 4 > 64 * 1024 or (refill and not bucketing) or (bucketing == 3 and not refill):
             continue
         yield dict(bucketing=bucketing, refill=refill, waves_per_group=waves, stack_depth=depth)
 

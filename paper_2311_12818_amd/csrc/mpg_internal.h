@@ -53,7 +53,8 @@ struct mpg_scene {
 };
 
 // persistent form: counter words per workspace, spatial cells per length
-#define MPG_WS_COUNTERS 128
+#define MPG_WS_COUNTERS 256
+#define MPG_MAX_PARTS 8
 #define MPG_CELL_RES 32
 #define MPG_CELLS (MPG_CELL_RES * MPG_CELL_RES * MPG_CELL_RES)
 
@@ -148,7 +149,7 @@ struct WalkIO {
 // finish, seeds, trials), batch bounding box.
 enum : int {
   CTR_HIST = 0, CTR_OFF = 16, CTR_CUR = 32, CTR_HEAD = 48, CTR_HEAD2 = 56, CTR_BOX = 64, CTR_HEAD3 = 72,
-  CTR_HEAD4 = 80
+  CTR_HEAD4 = 80, CTR_PHEAD = 128  // + (length - 1) * MPG_MAX_PARTS + part
 };
 
 // Pull the next 64-slot batch of a queue; wave-uniform result.

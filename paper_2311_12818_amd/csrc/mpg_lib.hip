@@ -398,7 +398,7 @@ mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams
   if (!(p->scale > 0.0f)) return fail(MPG_ERR_INVALID_ARG, "scale must be positive");
   if (!(p->tol_vertex >= 0.0f) || !(p->tol_residual >= 0.0f) || !(p->tmin_rel >= 0.0f) || !(p->match_rel >= 0.0f))
     return fail(MPG_ERR_INVALID_ARG, "negative tolerance");
-  if (p->bucketing < 0 || p->bucketing > 2) return fail(MPG_ERR_INVALID_ARG, "bucketing must be 0, 1 or 2");
+  if (p->bucketing < 0 || p->bucketing > 3) return fail(MPG_ERR_INVALID_ARG, "bucketing must be 0, 1, 2 or 3");
   if (p->waves_per_group != 1 && p->waves_per_group != 2 && p->waves_per_group != 4)
     return fail(MPG_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4");
   int need = s->max_depth + 1;

@@ -232,13 +232,19 @@ __global__ void __launch_bounds__(256) k_walk_persist(DevScene S, WalkParams P, 
 // trials and the queue is finite, so every wavefront leaves the loop.
 template <int N>
 __global__ void __launch_bounds__(256) k_walk_refill(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr,
-                                                     const int* perm) {
+                                                     const int* perm, int parts) {
   Stack stk = lane_stack(P.depth);
   const int start = ctr[CTR_OFF + N];
   const int count = ctr[CTR_HIST + N];
-  int* head = &ctr[CTR_HEAD + N - 1];
+  int* heads = &ctr[CTR_PHEAD + (N - 1) * MPG_MAX_PARTS];
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
+  // the bucket is split into `parts` consecutive slot ranges (spatial regions
+  // when the bucket is in Morton order); a workgroup starts on the range of
+  // its XCD (workgroups are dealt to the XCDs round robin) and moves on when
+  // that range is empty, so each XCD's L2 holds the part of the scene its
+  // region needs
+  int part = blockIdx.x % parts, tried = 0;
   int c = -1;
   bool drained = false;  // wave-uniform: the queue has no slot left for this wavefront
   WalkState<N> w;
@@ -248,12 +254,13 @@ __global__ void __launch_bounds__(256) k_walk_refill(DevScene S, WalkParams P, E
     const unsigned long long idle = __ballot(c < 0);
     if (idle && !drained) {
       const int nidle = __popcll(idle);
+      const int lo = (int)((long long)count * part / parts), hi = (int)((long long)count * (part + 1) / parts);
       int base = 0;
-      if (lane == 0) base = atomicAdd(head, nidle);
-      base = __shfl(base, 0, 64);
+      if (lane == 0) base = atomicAdd(&heads[part], nidle);
+      base = lo + __shfl(base, 0, 64);
       if (c < 0) {
         const int slot = base + __popcll(idle & below);
-        if (slot < count) {
+        if (slot < hi) {
           c = perm[start + slot];
           type = E.type[c];
           xD = ld_pt(E.xD, E.N, c);
@@ -266,7 +273,10 @@ __global__ void __launch_bounds__(256) k_walk_refill(DevScene S, WalkParams P, E
           }
         }
       }
-      if (base + nidle >= count) drained = true;
+      if (base + nidle >= hi) {  // this range is used up: the next one
+        part = part + 1 == parts ? 0 : part + 1;
+        if (++tried == parts) drained = true;
+      }
     }
     if (__ballot(c >= 0) == 0) {
       if (drained) break;
@@ -358,7 +368,8 @@ static persist_kernel_t persist_kernel(int n) {
     default: return k_walk_persist<8>;
   }
 }
-static persist_kernel_t refill_kernel(int n) {
+typedef void (*refill_kernel_t)(DevScene, WalkParams, EpView, WalkIO, int*, const int*, int);
+static refill_kernel_t refill_kernel(int n) {
   switch (n) {
     case 1: return k_walk_refill<1>;
     case 2: return k_walk_refill<2>;
@@ -448,7 +459,7 @@ static mpg_status bucket_chains(int bucketing, int max_len, int check_xl, const 
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
   HIP_TRY(hipGetLastError());
-  if (bucketing == 2) {
+  if (bucketing >= 2) {
     int* hist = ws->cells;
     int* cursor = ws->cells + KMAX * MPG_CELLS;
     hipLaunchKernelGGL(k_cells_zero, dim3(256), dim3(256), 0, stream, hist, KMAX * MPG_CELLS);
@@ -562,9 +573,16 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   // lengths round-robin over the side streams, longest first; each length's
   // finish pass follows its walk on the same stream
   for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) & 3) {
-    persist_kernel_t k = refill ? refill_kernel(n) : persist_kernel(n);
-    int grid = resident_blocks((const void*)k, threads, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
+    if (refill) {
+      refill_kernel_t k = refill_kernel(n);
+      int grid = resident_blocks((const void*)k, threads, lds);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm,
+                         bucketing == 3 ? MPG_MAX_PARTS : 1);
+    } else {
+      persist_kernel_t k = persist_kernel(n);
+      int grid = resident_blocks((const void*)k, threads, lds);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
+    }
     HIP_TRY(hipGetLastError());
     persist_kernel_t f = finish_persist_kernel(n);
     int fgrid = resident_blocks((const void*)f, threads, lds);

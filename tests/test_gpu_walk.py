@@ -213,8 +213,8 @@ def test_determinism(mpg):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("bucketing,waves,refill", [(1, 4, 0), (1, 1, 0), (0, 2, 0), (1, 4, 1), (1, 2, 1), (2, 1, 1),
-                                                   (2, 4, 0)])
+@pytest.mark.parametrize("bucketing,waves,refill", [(1, 4, 0), (1, 1, 0), (0, 2, 0), (1, 4, 1), (1, 2, 1),
+                                                   (2, 1, 1), (3, 4, 1), (2, 4, 0)])
 def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves, refill):
     """The persistent batched form computes every chain with the same code as
     the plain form, only scheduled differently: outputs are identical."""
