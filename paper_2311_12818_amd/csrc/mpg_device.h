@@ -327,10 +327,35 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
     float t = tri_test(rx, ry, rz, o, S.vpos[id.x], S.vpos[id.y], S.vpos[id.z]);
     if (t > tmin) take(h, cand, t);
   }
-  int sp = 0;
+  // traversal stack: the top entry lives in a register, the entries below it
+  // in the lane's LDS column, so a pop needs no LDS round trip (the reload of
+  // the next top is only waited for at the following pop)
+  int sp = 0, top = 0;
   int ref = 0;
+  bool done = false;
+  // Interior nodes and leaves in separate phases (Aila and Laine, HPG 2009,
+  // "while-while" with speculative traversal): a lane that reaches a leaf
+  // keeps it aside and goes on through interior nodes until every lane of
+  // the wavefront holds a leaf, then all test their leaf's triangles
+  // together.  The set of leaves tested, and so the hit, is unchanged; the
+  // step budget bounds the work of a malformed tree.
+  int leaf = 0;
+  bool have_leaf = false;
+  int budget = 8 * (S.n_nodes + S.n_tris) + 64;
   for (;;) {
-    if (ref >= 0) {
+    while (!done && (ref >= 0 || !have_leaf)) {
+      if (--budget < 0) return false;
+      if (ref < 0) {  // a leaf: set it aside, continue with the next entry
+        leaf = ref;
+        have_leaf = true;
+        if (sp == 0) {
+          done = true;
+          break;
+        }
+        ref = top;
+        if (--sp > 0) top = stk.base[(sp - 1) * 64];
+        continue;
+      }
       // 4-wide node: slab test of the four child boxes (SoA), then descend
       // into the nearest hit child and push the others, farthest first
       if (ref >= S.n_nodes) return false;
@@ -365,24 +390,30 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
       MPG_CSWAP(0, 1) MPG_CSWAP(2, 3) MPG_CSWAP(0, 2) MPG_CSWAP(1, 3) MPG_CSWAP(1, 2)
 #undef MPG_CSWAP
       if (tn[0] == INFINITY) {
-        if (sp == 0) break;
-        --sp;
-        ref = stk.base[sp * 64];
-        continue;
-      }
-#pragma unroll
-      for (int k = 3; k >= 1; --k) {
-        if (tn[k] != INFINITY) {
-          if (sp >= stk.depth) return false;
-          stk.base[sp * 64] = cr[k];
-          ++sp;
+        if (sp == 0) {
+          done = true;
+          break;
         }
+        ref = top;
+        if (--sp > 0) top = stk.base[(sp - 1) * 64];
+      } else {
+#pragma unroll
+        for (int k = 3; k >= 1; --k) {
+          if (tn[k] != INFINITY) {
+            if (sp >= stk.depth) return false;
+            if (sp > 0) stk.base[(sp - 1) * 64] = top;
+            top = cr[k];
+            ++sp;
+          }
+        }
+        ref = cr[0];
       }
-      ref = cr[0];
-      continue;
-    } else {
-      int start = ref & 0xFFFFFF;
-      int count = (ref >> 24) & 0x7F;
+      // every lane still traversing holds a leaf: test them together
+      if (__ballot(!have_leaf) == 0) break;
+    }
+    if (have_leaf) {
+      int start = leaf & 0xFFFFFF;
+      int count = (leaf >> 24) & 0x7F;
       if (start + count > S.n_tris) return false;
       for (int k = start; k < start + count; ++k) {
         float4 v0 = S.tri_v[3 * (size_t)k], v1 = S.tri_v[3 * (size_t)k + 1], v2 = S.tri_v[3 * (size_t)k + 2];
@@ -392,10 +423,9 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
         float t = tri_test(rx, ry, rz, o, v0, v1, v2);
         if (t > tmin) take(h, prim, t);
       }
+      have_leaf = false;
     }
-    if (sp == 0) break;
-    --sp;
-    ref = stk.base[sp * 64];
+    if (done) break;
   }
   return true;
 }
