@@ -29,10 +29,11 @@
  *  - The persistent form (MPG_FORM_PERSISTENT) keeps its bucket order, queue
  *    heads and counters in an mpg_workspace: a workspace serves one call at a
  *    time (calls on one stream are ordered; calls on different streams need
- *    different workspaces).  Its per-length kernels run on four internal
- *    streams per device, forked from and joined back to hip_stream with
- *    events, which graph capture records as dependencies; such calls must not
- *    be issued from several host threads on one device at the same time.
+ *    different workspaces).  Its per-length kernels run on hip_stream and
+ *    three internal streams per device, forked from and joined back to
+ *    hip_stream with events, which graph capture records as dependencies;
+ *    such calls must not be issued from several host threads on one device
+ *    at the same time.
  */
 #ifndef MPG_H
 #define MPG_H

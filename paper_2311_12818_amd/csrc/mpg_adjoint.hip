@@ -368,16 +368,16 @@ extern "C" mpg_status manifold_walk_adjoint(const mpg_scene* s, const mpg_walk_p
                        p->max_len, cls);
     HIP_TRY(hipGetLastError());
     if ((st = bucket_classes(E.N, cls, ws, (hipStream_t)stream)) != MPG_OK) return st;
-    hipStream_t side[4];
-    if ((st = side_fork((hipStream_t)stream, side)) != MPG_OK) return st;
-    for (int n = p->max_len, q = 0; n >= 1; --n, q = (q + 1) & 3) {
+    hipStream_t wk[MPG_WORKERS];
+    if ((st = workers_fork((hipStream_t)stream, wk)) != MPG_OK) return st;
+    for (int n = p->max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
       adj_persist_t k = adjoint_persist_kernel(n);
       int grid = resident_blocks((const void*)k, threads, 0);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), 0, side[q], s->dev, P, E, io, ws->counters,
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), 0, wk[q], s->dev, P, E, io, ws->counters,
                          (const int*)ws->perm);
       HIP_TRY(hipGetLastError());
     }
-    return side_join((hipStream_t)stream);
+    return workers_join((hipStream_t)stream);
   }
   const int threads = 256;  // k_adjoint's launch bound
   hipLaunchKernelGGL(adjoint_kernel(p->max_len), dim3((E.N + threads - 1) / threads), dim3(threads), 0,

@@ -52,6 +52,14 @@ struct mpg_scene {
   uint32_t* zmax_bits = nullptr;
 };
 
+// Lower bound on resident wavefronts per SIMD for the lane-refill kernels of
+// chain length n (amdgpu_waves_per_eu): the compiler keeps such a kernel
+// within 512 / waves registers per lane and spills the rest.  A refill walk
+// spends most of its time waiting on ray-traversal loads, so more wavefronts
+// in flight outweigh the spill traffic: lengths 1-2 at 5 (96 registers,
+// against the compiler's own 4) and lengths 6-8 at 2 (256, against 1).
+constexpr int refill_waves(int n) { return n <= 2 ? 5 : (n >= 6 ? 2 : 1); }
+
 // persistent form: counter words per workspace, spatial cells per length
 #define MPG_WS_COUNTERS 256
 #define MPG_MAX_PARTS 8
@@ -161,11 +169,15 @@ __device__ __forceinline__ int next_batch(int* head) {
 
 // persistent-form helpers (mpg_persistent.hip): resident workgroups of a
 // kernel across the device, length buckets of precomputed classes (1..8, 0 =
-// none) in ws->perm and ws->counters, fork / join of the four side streams
+// none) in ws->perm and ws->counters
 int resident_blocks(const void* fn, int threads, size_t lds);
 mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream_t stream);
-mpg_status side_fork(hipStream_t stream, hipStream_t side[4]);
-mpg_status side_join(hipStream_t stream);
+// per-length kernels run on MPG_WORKERS streams: wk[0] is the caller's
+// stream, the others internal streams of the device that wait for the work
+// queued on it so far; workers_join makes the caller's stream wait for them
+#define MPG_WORKERS 4
+mpg_status workers_fork(hipStream_t stream, hipStream_t wk[MPG_WORKERS]);
+mpg_status workers_join(hipStream_t stream);
 
 // host-side checks shared by every entry point
 mpg_status walk_io(const mpg_chains* chains, const mpg_walk_out* wout, WalkIO* io);

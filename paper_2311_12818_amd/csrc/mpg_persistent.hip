@@ -231,8 +231,8 @@ __global__ void __launch_bounds__(256) k_walk_persist(DevScene S, WalkParams P, 
 // by their rank in the ballot.  Every lane's chain ends within max_iter
 // trials and the queue is finite, so every wavefront leaves the loop.
 template <int N>
-__global__ void __launch_bounds__(256) k_walk_refill(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr,
-                                                     const int* perm, int parts) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(refill_waves(N))))
+k_walk_refill(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr, const int* perm, int parts) {
   Stack stk = lane_stack(P.depth);
   const int start = ctr[CTR_OFF + N];
   const int count = ctr[CTR_HIST + N];
@@ -417,14 +417,16 @@ int resident_blocks(const void* fn, int threads, size_t lds) {
   return std::max(1, cus) * per;
 }
 
-// Internal streams of the current device for the per-length kernels (four:
-// the runtime exposes four hardware queues per process by default).  All at
-// the default priority; fork / join through events, which graph capture
+// Workers for the per-length kernels: the caller's stream and three internal
+// streams of the current device.  The runtime gives a process four hardware
+// queues by default; the caller's stream holds one, so a fourth internal
+// stream would share a queue (and its in-order execution) with another.  All
+// at the default priority; fork / join through events, which graph capture
 // records as dependencies.
 struct SideStreams {
   int device = -1;
-  hipStream_t s[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t s[MPG_WORKERS - 1] = {};
+  hipEvent_t fork = nullptr, join[MPG_WORKERS - 1] = {};
 };
 static SideStreams g_side[64];
 static std::mutex g_side_mu;
@@ -436,7 +438,7 @@ static mpg_status side_streams(SideStreams** out) {
   std::lock_guard<std::mutex> lock(g_side_mu);
   SideStreams& ss = g_side[dev];
   if (ss.device != dev) {
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < MPG_WORKERS - 1; ++k) {
       HIP_TRY(hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking));
       HIP_TRY(hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming));
     }
@@ -444,6 +446,30 @@ static mpg_status side_streams(SideStreams** out) {
     ss.device = dev;
   }
   *out = &ss;
+  return MPG_OK;
+}
+
+mpg_status workers_fork(hipStream_t stream, hipStream_t wk[MPG_WORKERS]) {
+  SideStreams* ss;
+  mpg_status st = side_streams(&ss);
+  if (st != MPG_OK) return st;
+  HIP_TRY(hipEventRecord(ss->fork, stream));
+  wk[0] = stream;
+  for (int k = 0; k < MPG_WORKERS - 1; ++k) {
+    HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
+    wk[k + 1] = ss->s[k];
+  }
+  return MPG_OK;
+}
+
+mpg_status workers_join(hipStream_t stream) {
+  SideStreams* ss;
+  mpg_status st = side_streams(&ss);
+  if (st != MPG_OK) return st;
+  for (int k = 0; k < MPG_WORKERS - 1; ++k) {
+    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
+    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
+  }
   return MPG_OK;
 }
 
@@ -493,23 +519,17 @@ mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide
   io.status = status;
   mpg_status bst = bucket_chains(bucketing, KMAX, 0, E, io, ws, stream);
   if (bst != MPG_OK) return bst;
-  SideStreams* ss;
-  mpg_status st = side_streams(&ss);
+  hipStream_t wk[MPG_WORKERS];
+  mpg_status st = workers_fork(stream, wk);
   if (st != MPG_OK) return st;
-  HIP_TRY(hipEventRecord(ss->fork, stream));
-  for (int k = 0; k < 4; ++k) HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
-  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) & 3) {
+  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     seeds_kernel_t k = seeds_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, G, has_guide, P, E, seed,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, has_guide, P, E, seed,
                        (uint64_t)trial, alpha, prim_out, pos_out, status, ctr, (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }
-  for (int k = 0; k < 4; ++k) {
-    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
-    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
-  }
-  return MPG_OK;
+  return workers_join(stream);
 }
 
 mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream_t stream) {
@@ -523,29 +543,6 @@ mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, N, cls, ctr, ws->perm);
   HIP_TRY(hipGetLastError());
-  return MPG_OK;
-}
-
-mpg_status side_fork(hipStream_t stream, hipStream_t side[4]) {
-  SideStreams* ss;
-  mpg_status st = side_streams(&ss);
-  if (st != MPG_OK) return st;
-  HIP_TRY(hipEventRecord(ss->fork, stream));
-  for (int k = 0; k < 4; ++k) {
-    HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
-    side[k] = ss->s[k];
-  }
-  return MPG_OK;
-}
-
-mpg_status side_join(hipStream_t stream) {
-  SideStreams* ss;
-  mpg_status st = side_streams(&ss);
-  if (st != MPG_OK) return st;
-  for (int k = 0; k < 4; ++k) {
-    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
-    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
-  }
   return MPG_OK;
 }
 
@@ -565,33 +562,31 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   }
   mpg_status bst = bucket_chains(bucketing, max_len, 1, E, io, ws, stream);
   if (bst != MPG_OK) return bst;
-  SideStreams* ss;
-  mpg_status st = side_streams(&ss);
+  hipStream_t wk[MPG_WORKERS];
+  mpg_status st = workers_fork(stream, wk);
   if (st != MPG_OK) return st;
-  HIP_TRY(hipEventRecord(ss->fork, stream));
-  for (int k = 0; k < 4; ++k) HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
-  // lengths round-robin over the side streams, longest first; each length's
-  // finish pass follows its walk on the same stream
-  for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) & 3) {
+  // lengths round-robin over the workers, longest first; every finish pass
+  // is queued after all walks, on its walk's worker.  A finish pass launched
+  // while other lengths' persistent walks hold the compute units gets few
+  // slots and holds up the walks queued behind it on its worker.
+  for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     if (refill) {
       refill_kernel_t k = refill_kernel(n);
       int grid = resident_blocks((const void*)k, threads, lds);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm,
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, P, E, io, ctr, (const int*)ws->perm,
                          bucketing == 3 ? MPG_MAX_PARTS : 1);
     } else {
       persist_kernel_t k = persist_kernel(n);
       int grid = resident_blocks((const void*)k, threads, lds);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
     }
     HIP_TRY(hipGetLastError());
+  }
+  for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     persist_kernel_t f = finish_persist_kernel(n);
     int fgrid = resident_blocks((const void*)f, threads, lds);
-    hipLaunchKernelGGL(f, dim3(fgrid), dim3(threads), lds, ss->s[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
+    hipLaunchKernelGGL(f, dim3(fgrid), dim3(threads), lds, wk[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }
-  for (int k = 0; k < 4; ++k) {
-    HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
-    HIP_TRY(hipStreamWaitEvent(stream, ss->join[k], 0));
-  }
-  return MPG_OK;
+  return workers_join(stream);
 }

@@ -232,16 +232,16 @@ static mpg_status inv_persistent(const mpg_scene* s, const DevGuide& G, int has_
   HIP_TRY(hipGetLastError());
   mpg_status st = bucket_classes(E.N, cls, ws, stream);
   if (st != MPG_OK) return st;
-  hipStream_t side[4];
-  if ((st = side_fork(stream, side)) != MPG_OK) return st;
-  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) & 3) {
+  hipStream_t wk[MPG_WORKERS];
+  if ((st = workers_fork(stream, wk)) != MPG_OK) return st;
+  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     inv_kernel_t k = inv_refill_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, side[q], s->dev, G, has_guide, P, E, io, ws->counters,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, has_guide, P, E, io, ws->counters,
                        (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }
-  return side_join(stream);
+  return workers_join(stream);
 }
 
 extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, const mpg_walk_params* p,
