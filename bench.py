@@ -79,7 +79,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-TUNED_KNOBS = ("bucketing", "refill", "waves_per_group", "stack_depth")
+TUNED_KNOBS = ("bucketing", "refill", "waves_per_group", "stack_depth", "length_order")
 
 
 def load_tuned(path, workload):
@@ -234,7 +234,7 @@ def adjoint_leg(M, W, args, tuned_all, cone):
     kw = dict(cone_cos=cone, max_len=4, defer_fp64=1, form=M.FORM_PERSISTENT)
     for k in TUNED_KNOBS:
         if k in tuned_all:
-            kw[k] = int(tuned_all[k])
+            kw[k] = tuned_all[k] if k == "length_order" else int(tuned_all[k])
     prm = M.walk_params(sc.scale, **kw)
     ws = M.Workspace(n)
     prim, pos = M.empty_chains(n)
@@ -317,7 +317,7 @@ def main():
         if form == "persistent":
             for k in TUNED_KNOBS:
                 if k in tuned:
-                    kw[k] = int(tuned[k])
+                    kw[k] = tuned[k] if k == "length_order" else int(tuned[k])
         return M.walk_params(sc.scale, **kw)
 
     ws = M.Workspace(N)

@@ -36,6 +36,7 @@ class MPGError(RuntimeError):
 P = C.c_void_p
 I32 = C.c_int32
 F32 = C.c_float
+U32 = C.c_uint32
 
 
 class mpg_heightfield(C.Structure):
@@ -67,7 +68,7 @@ class mpg_walk_params(C.Structure):
     _fields_ = [("max_iter", I32), ("tol_vertex", F32), ("tol_residual", F32), ("scale", F32), ("tmin_rel", F32),
                 ("match_rel", F32), ("fp64_cond_threshold", F32), ("fp64_graze_cos", F32), ("cone_cos", F32), ("form", I32),
                 ("bucketing", I32), ("waves_per_group", I32), ("stack_depth", I32), ("refill", I32),
-                ("max_len", I32), ("defer_fp64", I32)]
+                ("max_len", I32), ("defer_fp64", I32), ("length_order", U32)]
 
 
 class mpg_guide_desc(C.Structure):
@@ -246,10 +247,23 @@ class Guide:
             self.h = None
 
 
+def pack_length_order(lengths) -> int:
+    """The ``length_order`` word of a launch order of the lengths 1..8 (the
+    first length in the lowest nibble)."""
+    lengths = [int(n) for n in lengths]
+    if sorted(lengths) != list(range(1, 9)):
+        raise ValueError("length order must hold every length 1..8 once")
+    return sum(n << (4 * k) for k, n in enumerate(lengths))
+
+
 def walk_params(scale: float, **kw) -> mpg_walk_params:
+    """Defaults for a scene of scale ``scale`` with fields overridden by ``kw``
+    (``length_order`` may be given as a list of the lengths 1..8)."""
     p = mpg_walk_params()
     _check(lib().mpg_walk_params_default(float(scale), C.byref(p)), "mpg_walk_params_default")
     for k, v in kw.items():
+        if k == "length_order" and isinstance(v, (list, tuple)):
+            v = pack_length_order(v)
         setattr(p, k, v)
     return p
 

@@ -246,6 +246,7 @@ extern "C" mpg_status mpg_walk_params_default(float scale, mpg_walk_params* p) {
   p->refill = 0;
   p->max_len = KMAX;
   p->defer_fp64 = 0;
+  p->length_order = 0;
   return MPG_OK;
 }
 
@@ -419,6 +420,11 @@ mpg_status check_params(const mpg_scene* s, const mpg_walk_params* p, WalkParams
   w->depth = depth;
   *waves = p->waves_per_group;
   if (p->max_len < 1 || p->max_len > KMAX) return fail(MPG_ERR_INVALID_ARG, "max_len outside 1..8");
+  if (p->length_order != 0) {
+    unsigned seen = 0;
+    for (int k = 0; k < KMAX; ++k) seen |= 1u << ((p->length_order >> (4 * k)) & 15u);
+    if (seen != 0x1FEu) return fail(MPG_ERR_INVALID_ARG, "length_order is not a permutation of the lengths 1..8");
+  }
   return MPG_OK;
 }
 
@@ -486,7 +492,8 @@ extern "C" mpg_status manifold_walk_batch(const mpg_scene* s, const mpg_walk_par
   dim3 grid((E.N + threads - 1) / threads);
   if (p->form == MPG_FORM_PERSISTENT) {
     if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "manifold_walk_batch: workspace too small");
-    mpg_status st2 = walk_persistent(s, P, waves, p->bucketing, p->refill, p->max_len, E, io, ws, (hipStream_t)stream);
+    mpg_status st2 = walk_persistent(s, P, waves, p->bucketing, p->refill, p->max_len, p->length_order, E, io, ws,
+                                     (hipStream_t)stream);
     if (st2 != MPG_OK) return st2;
   } else if (p->form == MPG_FORM_PLAIN) {
     hipLaunchKernelGGL(plain_kernel(p->max_len), grid, dim3(threads), lds, (hipStream_t)stream, s->dev, P, E, io);

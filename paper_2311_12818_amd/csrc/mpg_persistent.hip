@@ -547,7 +547,8 @@ mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream
 }
 
 mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
-                           int max_len, const EpView& E, const WalkIO& io, mpg_workspace* ws, hipStream_t stream) {
+                           int max_len, uint32_t length_order, const EpView& E, const WalkIO& io, mpg_workspace* ws,
+                           hipStream_t stream) {
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
   int* ctr = ws->counters;
@@ -565,11 +566,18 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   hipStream_t wk[MPG_WORKERS];
   mpg_status st = workers_fork(stream, wk);
   if (st != MPG_OK) return st;
-  // lengths round-robin over the workers, longest first; every finish pass
+  // lengths dealt round robin to the workers in launch order (length_order,
+  // else longest first; lengths above max_len left out); every finish pass
   // is queued after all walks, on its walk's worker.  A finish pass launched
   // while other lengths' persistent walks hold the compute units gets few
   // slots and holds up the walks queued behind it on its worker.
-  for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+  int order[KMAX], n_order = 0;
+  for (int k = 0; k < KMAX; ++k) {
+    int n = length_order ? (int)((length_order >> (4 * k)) & 15u) : KMAX - k;
+    if (n <= max_len) order[n_order++] = n;
+  }
+  for (int j = 0; j < n_order; ++j) {
+    const int n = order[j], q = j % MPG_WORKERS;
     if (refill) {
       refill_kernel_t k = refill_kernel(n);
       int grid = resident_blocks((const void*)k, threads, lds);
@@ -582,7 +590,8 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
     }
     HIP_TRY(hipGetLastError());
   }
-  for (int n = max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+  for (int j = 0; j < n_order; ++j) {
+    const int n = order[j], q = j % MPG_WORKERS;
     persist_kernel_t f = finish_persist_kernel(n);
     int fgrid = resident_blocks((const void*)f, threads, lds);
     hipLaunchKernelGGL(f, dim3(fgrid), dim3(threads), lds, wk[q], s->dev, P, E, io, ctr, (const int*)ws->perm);

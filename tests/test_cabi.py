@@ -44,3 +44,42 @@ def test_host_side_errors_without_gpu():
     assert p.max_iter == 20 and abs(p.tol_vertex - 1e-4) < 1e-9 and p.max_len == 8
     assert L.manifold_walk_batch(None, ctypes.byref(p), None, None, None, None, None, None, None) == -1
     assert L.sample_seeds(None, None, None, None, 0, 0, 0.5, None, None, None, None) == -1
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    import paper_2311_12818_amd as M
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [M.mpg_heightfield, M.mpg_scene_desc, M.mpg_endpoints, M.mpg_chains, M.mpg_walk_out,
+               M.mpg_walk_params, M.mpg_guide_desc]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mpg.h"', "int main(void) {"]
+    expect = []
+    for S in structs:
+        name = S.__name__
+        lines.append('printf("%%zu\\n", sizeof(%s));' % name)
+        expect.append(ctypes.sizeof(S))
+        for field in S._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (name, field[0]))
+            expect.append(getattr(S, field[0]).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == expect
+
+
+def test_length_order_default_and_packing():
+    import paper_2311_12818_amd as M
+    p = M.walk_params(2.0)
+    assert p.length_order == 0
+    assert M.pack_length_order([8, 7, 6, 5, 4, 3, 2, 1]) == 0x12345678
+    assert M.walk_params(2.0, length_order=[3, 8, 7, 6, 5, 4, 2, 1]).length_order == 0x12456783
+    with pytest.raises(ValueError):
+        M.pack_length_order([1, 1, 2, 3, 4, 5, 6, 7])

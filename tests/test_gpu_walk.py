@@ -237,6 +237,36 @@ def test_persistent_form_matches_plain_bit_for_bit(mpg, bucketing, waves, refill
     GC.compare_walks(ep, pers, o, sc.scale, tag="slab_persistent")
 
 
+@pytest.mark.parametrize("order,max_len", [([3, 8, 7, 6, 5, 4, 2, 1], 8), ([1, 2, 3, 4, 5, 6, 7, 8], 8),
+                                           ([2, 8, 7, 6, 5, 4, 3, 1], 5)])
+def test_length_order_changes_scheduling_only(mpg, order, max_len):
+    """The order in which the per-length kernels are dealt to the workers
+    leaves every output unchanged (also with lengths above max_len, which are
+    skipped and whose chains are bad input)."""
+    sc = W.slab_stack_scene()
+    ep = W.slab_uneven_endpoints(12000 + 5)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    kw = dict(form=mpg.FORM_PERSISTENT, bucketing=1, refill=1, waves_per_group=1, max_len=max_len)
+    ref = run_gpu_walk(mpg, sc, ep, prim, pos, st, **kw)
+    got = run_gpu_walk(mpg, sc, ep, prim, pos, st, length_order=order, **kw)
+    for k in ("status", "iters", "sol", "G", "kappa", "residual"):
+        assert np.array_equal(ref[k], got[k]), k
+    ok = ref["status"] != mpg.BAD_INPUT
+    assert np.array_equal(ref["prim"][:, ok], got["prim"][:, ok])
+    assert np.array_equal(ref["pos"][:, :, ok], got["pos"][:, :, ok])
+    assert (ref["status"][ep.length > max_len] == mpg.BAD_INPUT).all()
+
+
+def test_length_order_must_be_a_permutation(mpg):
+    sc = W.slab_stack_scene()
+    ep = W.slab_uneven_endpoints(256)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    with pytest.raises(mpg.MPGError, match="length_order"):
+        run_gpu_walk(mpg, sc, ep, prim, pos, st, form=mpg.FORM_PERSISTENT, length_order=0x12345677)
+
+
 def test_deferred_fp64_pass(mpg):
     """defer_fp64 leaves NEEDS_FP64 chains; manifold_walk_fp64 finishes them
     exactly as the one-call walk does."""
