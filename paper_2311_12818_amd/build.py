@@ -10,9 +10,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpg.so")
-SOURCES = ["mpg_lib.hip", "mpg_persistent.hip", "mpg_guide.hip", "mpg_adjoint.hip", "mpg_params.hip",
+SOURCES = ["mpg_lib.hip", "mpg_persistent.hip", "mpg_guide.hip", "mpg_adjoint.hip", "mpg_adjoint_plain.hip", "mpg_params.hip",
            "mpg_count.hip", "mpg_trials.hip", "mpg_scene.cpp"]
-HEADERS = ["mpg_device.h", "mpg_internal.h", "mpg_walk.h", "mpg_scene.h"]
+HEADERS = ["mpg_device.h", "mpg_internal.h", "mpg_walk.h", "mpg_scene.h", "mpg_adjoint.h"]
 DEPS = SOURCES + HEADERS
 
 HIPCC_FLAGS = [
