@@ -195,7 +195,7 @@ typedef struct {
   int32_t max_len;           /* longest chain in the batch (1..8, default 8); longer chains get MPG_BAD_INPUT */
   int32_t defer_fp64;        /* 1: leave MPG_NEEDS_FP64 chains for a later manifold_walk_fp64 call (0) */
   uint32_t length_order;     /* persistent form with bucketing: the order in which the per-length walk
-                                kernels are dealt round robin to the four workers (the caller's stream and
+                                and seed kernels are dealt round robin to the four workers (the caller's stream and
                                 three internal streams), as eight 4-bit lengths, the first in the lowest
                                 nibble; every length 1..8 exactly once (lengths above max_len are skipped).
                                 0 = longest first (0x12345678).  Results do not depend on it. */

@@ -456,8 +456,8 @@ extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const
   if (g) G = g->dev();
   if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
     if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: workspace too small");
-    return seeds_persistent(s, G, g ? 1 : 0, P, waves, p->bucketing, E, philox_seed, trial, alpha, out->d_prim,
-                            out->d_pos, d_status, ws, (hipStream_t)stream);
+    return seeds_persistent(s, G, g ? 1 : 0, P, waves, p->bucketing, p->length_order, E, philox_seed, trial, alpha,
+                            out->d_prim, out->d_pos, d_status, ws, (hipStream_t)stream);
   }
   int threads = 64 * waves;
   size_t lds = (size_t)waves * P.depth * 64 * 4;

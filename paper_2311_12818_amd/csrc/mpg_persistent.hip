@@ -505,9 +505,20 @@ static mpg_status bucket_chains(int bucketing, int max_len, int check_xl, const 
   return MPG_OK;
 }
 
+// The lengths 1..max_len in launch order: the nibbles of length_order (the
+// first in the lowest), else longest first.
+static int launch_order(uint32_t length_order, int max_len, int order[KMAX]) {
+  int n_order = 0;
+  for (int k = 0; k < KMAX; ++k) {
+    int n = length_order ? (int)((length_order >> (4 * k)) & 15u) : KMAX - k;
+    if (n <= max_len) order[n_order++] = n;
+  }
+  return n_order;
+}
+
 mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P, int waves,
-                            int bucketing, const EpView& E, uint64_t seed, uint32_t trial, float alpha,
-                            int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,
+                            int bucketing, uint32_t length_order, const EpView& E, uint64_t seed, uint32_t trial,
+                            float alpha, int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,
                             hipStream_t stream) {
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
@@ -522,7 +533,11 @@ mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide
   hipStream_t wk[MPG_WORKERS];
   mpg_status st = workers_fork(stream, wk);
   if (st != MPG_OK) return st;
-  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+  // lengths dealt round robin to the workers in launch order
+  int order[KMAX];
+  const int n_order = launch_order(length_order, KMAX, order);
+  for (int j = 0; j < n_order; ++j) {
+    const int n = order[j], q = j % MPG_WORKERS;
     seeds_kernel_t k = seeds_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, has_guide, P, E, seed,
@@ -571,11 +586,8 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   // is queued after all walks, on its walk's worker.  A finish pass launched
   // while other lengths' persistent walks hold the compute units gets few
   // slots and holds up the walks queued behind it on its worker.
-  int order[KMAX], n_order = 0;
-  for (int k = 0; k < KMAX; ++k) {
-    int n = length_order ? (int)((length_order >> (4 * k)) & 15u) : KMAX - k;
-    if (n <= max_len) order[n_order++] = n;
-  }
+  int order[KMAX];
+  const int n_order = launch_order(length_order, max_len, order);
   for (int j = 0; j < n_order; ++j) {
     const int n = order[j], q = j % MPG_WORKERS;
     if (refill) {

@@ -310,8 +310,8 @@ def test_counting_walk_matches_and_counts(mpg):
     assert counts["vertex_jacobian_evals"] > 0 and counts["vertex_residual_evals"] > 0
 
 
-@pytest.mark.parametrize("bucketing", [1, 2])
-def test_persistent_seeds_match_plain_seeds(mpg, bucketing):
+@pytest.mark.parametrize("bucketing,order", [(1, 0), (2, 0), (1, [3, 8, 7, 6, 5, 4, 2, 1])])
+def test_persistent_seeds_match_plain_seeds(mpg, bucketing, order):
     """Seeds drawn by the persistent per-length kernels equal the plain
     launch's bit for bit (same routine, same Philox counters)."""
     import torch
@@ -321,7 +321,8 @@ def test_persistent_seeds_match_plain_seeds(mpg, bucketing):
     scene = mpg.Scene(sc)
     dep = mpg.Endpoints(ep)
     plain = mpg.walk_params(sc.scale, cone_cos=GC.cone_cos())
-    pers = mpg.walk_params(sc.scale, cone_cos=GC.cone_cos(), form=mpg.FORM_PERSISTENT, bucketing=bucketing)
+    pers = mpg.walk_params(sc.scale, cone_cos=GC.cone_cos(), form=mpg.FORM_PERSISTENT, bucketing=bucketing,
+                           length_order=order)
     ws = mpg.Workspace(ep.n)
     a = mpg.sample_seeds(scene, dep, plain, seed=9, trial=2)
     b = mpg.sample_seeds(scene, dep, pers, seed=9, trial=2, ws=ws)

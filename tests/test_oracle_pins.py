@@ -628,3 +628,31 @@ def test_em_cells_and_min_samples(oracle_lib):
     gd = O.fit_guide(s, lo, hi, res=2, iters=5, min_samples=16)
     assert gd.valid[0] == 1 and gd.valid[1:].sum() == 0
     assert gd.count[0] == 3000
+
+
+def test_newton_converges_quadratically_on_the_smooth_mirror(oracle_lib):
+    # Newton's method on the constraints (Sec. 4) converges quadratically near
+    # a solution of a smooth manifold: for accepted full steps the residual
+    # obeys |C_{k+1}| <= c |C_k|^2.  The walk is re-run with max_iter = k to
+    # read the chain after k trials.  A Jacobian that is off (a dropped term,
+    # a transposed block) still converges, but only linearly, which puts the
+    # ratio |C_{k+1}| / |C_k|^2 above 1e3 once |C_k| < 1e-3.
+    sc = W.sphere_mirror_scene()
+    ep = W.sphere_mirror_endpoints(1024)
+    osc = O.Scene(sc)
+    cone = math.cos(math.radians(W.SEED_CONE_DEG))
+    prim, pos, st = O.sample_seeds(osc, ep, prm=O.params(sc.scale, cone_cos=cone))
+    pos = pos.astype(np.float32)
+    K = 12
+    res = np.full((K + 1, ep.n), np.nan)
+    for k in range(1, K + 1):
+        r = O.walk(osc, ep, prim, pos, st, polish=False, prm=O.params(sc.scale, cone_cos=cone, max_iter=k))
+        for c in np.nonzero((r["status"] == O.CONVERGED) | (r["status"] == O.MAX_ITER))[0]:
+            Cv, _, _ = O.constraint(osc, 1, int(ep.types[c]), ep.xD[:, c].astype(np.float64),
+                                    ep.xL[:, c].astype(np.float64), r["prim"][:1, c], r["pos"][:, :1, c].T)
+            res[k, c] = np.abs(Cv).max()
+    a, b = res[:-1], res[1:]
+    near = np.isfinite(a) & np.isfinite(b) & (b > 1e-12) & (b < a) & (a < 1e-3)
+    ratio = b[near] / a[near] ** 2
+    assert ratio.size > 100
+    assert np.median(ratio) < 50 and np.percentile(ratio, 90) < 200
