@@ -353,8 +353,9 @@ def main():
         walk_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
         fp64_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
         st = outs["status"].cpu().numpy()
+        iters = outs["iters"].cpu().numpy()
         return dict(wall=wall, ms_per_step=1e3 * wall / steps, seeds_ms=seeds_ms, walk_ms=walk_ms, fp64_ms=fp64_ms,
-                    status=st)
+                    status=st, iters=iters)
 
     main_form = args.form
     R = timed(main_form, args.steps, args.warmup)
@@ -437,6 +438,11 @@ def main():
         "config": {"workload": name, "chains": N, "scene_tris": int(sc.n_tris), "max_len": MAX_LEN[name],
                    "form": headline_form, "converged_fraction": n_conv / N, "tuned": tuned},
         "per_k": per_k,
+        # outcome of every chain of the main form's last step, and the Newton
+        # trials the walks used (index = trials)
+        "status_hist": {(M.STATUS_NAMES + ["needs_fp64"])[k]: int(v)
+                        for k, v in enumerate(np.bincount(R["status"].astype(np.int64), minlength=1)) if v},
+        "iters_hist": np.bincount(R["iters"].astype(np.int64), minlength=1).tolist(),
         "forms": forms,
         "roofline": roofline,
     }
