@@ -87,9 +87,10 @@ __global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int ha
 // ---------------------------------------------------------------------------
 // Persistent form of the trials: chains with a converged target are bucketed
 // by length; each lane owns one target chain and advances its current trial
-// walk by one walk_step per turn, starting the next trial (or taking the
-// next chain) as soon as the walk ends, so lanes do not idle while the
-// chain with the most trials of a batch finishes.  Same seeds, walks,
+// walk by one walk_step per turn; a lane whose walk has ended takes the next
+// chain at once if its target is done, and starts its next trial together
+// with the other waiting lanes of its wavefront, so lanes do not idle while
+// the chain with the most trials of a batch finishes.  Same seeds, walks,
 // matches and counts as inv_one.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_inv_classify(EpView E, InvIO io, int8_t* cls) {
@@ -160,7 +161,17 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, int 
       if (drained) break;
       continue;
     }
-    if (c >= 0 && !walking) {
+    // A new trial starts with seed sampling (a guided lift ray and the
+    // deduction rays), traversals that the lanes in the middle of a walk sit
+    // out.  Lanes waiting for a new trial therefore start together, once
+    // they are at least half of the busy lanes (or no lane is walking); each
+    // trial's seed depends on (chain, trial) only, so the results do not
+    // change.  On the guided water batch: 114 against 123 ms on average over
+    // five runs each (run-to-run spread about 5%).
+    const unsigned long long waiting = __ballot(c >= 0 && !walking);
+    const unsigned long long busy = __ballot(c >= 0);
+    const bool start_trials = 2 * __popcll(waiting) >= __popcll(busy);
+    if (c >= 0 && !walking && start_trials) {
       if (k == io.max_trials) {  // no match within the budget: K = max_trials, truncated
         trunc = true;
         total += io.max_trials;
