@@ -1137,7 +1137,8 @@ __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G,
   U8 U = philox_uniforms(seed, chain, trial, 0);
   f3 pt;
   bool ok = false;
-  int cell = G ? guide_cell(*G, xD) : -1;
+  // a guide without a cell table (valid == nullptr) stands for p_0 only
+  int cell = G && G->valid ? guide_cell(*G, xD) : -1;
   bool guided = G && cell >= 0 && G->valid[cell] && !(U.u[0] < alpha);
   if (guided) ok = guided_point(S, *G, cell, seed, chain, trial, U, stk, pt);
   if (!ok) ok = p0_point(S, P, obj1, xD, nD, U.u[1], U.u[2], U.u[3], pt);

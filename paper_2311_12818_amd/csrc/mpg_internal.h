@@ -188,7 +188,7 @@ mpg_status check_endpoints(const mpg_endpoints* e, EpView* v);
 mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, int bucketing, int refill,
                            int max_len, uint32_t length_order, const EpView& E, const WalkIO& io, mpg_workspace* ws,
                            hipStream_t stream);
-mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P, int waves,
+mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, const WalkParams& P, int waves,
                             int bucketing, uint32_t length_order, const EpView& E, uint64_t seed, uint32_t trial,
                             float alpha,
                             int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,

@@ -278,7 +278,7 @@ extern "C" void mpg_workspace_destroy(mpg_workspace* w) {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-__global__ void k_sample_seeds(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E, uint64_t seed,
+__global__ void k_sample_seeds(DevScene S, DevGuide G, WalkParams P, EpView E, uint64_t seed,
                                uint64_t trial, float alpha, int32_t* prim_out, float* pos_out, int8_t* st) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   Stack stk = lane_stack(P.depth);
@@ -288,7 +288,9 @@ __global__ void k_sample_seeds(DevScene S, DevGuide G, int has_guide, WalkParams
     st[c] = ST_BAD_INPUT;
     return;
   }
-  const DevGuide* g = has_guide ? &G : nullptr;
+  // always the argument's address (no guide: a zeroed DevGuide); a pointer
+  // that may be null would make the compiler copy G to private memory
+  const DevGuide* g = &G;
   switch (n) {
     case 1: seed_one<1>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
     case 2: seed_one<2>(S, g, P, E, c, seed, trial, alpha, prim_out, pos_out, st, stk); break;
@@ -456,13 +458,13 @@ extern "C" mpg_status sample_seeds(const mpg_scene* s, const mpg_guide* g, const
   if (g) G = g->dev();
   if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
     if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "sample_seeds: workspace too small");
-    return seeds_persistent(s, G, g ? 1 : 0, P, waves, p->bucketing, p->length_order, E, philox_seed, trial, alpha,
+    return seeds_persistent(s, G, P, waves, p->bucketing, p->length_order, E, philox_seed, trial, alpha,
                             out->d_prim, out->d_pos, d_status, ws, (hipStream_t)stream);
   }
   int threads = 64 * waves;
   size_t lds = (size_t)waves * P.depth * 64 * 4;
   hipLaunchKernelGGL(k_sample_seeds, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
-                     s->dev, G, g ? 1 : 0, P, E, philox_seed, (uint64_t)trial, alpha, out->d_prim, out->d_pos,
+                     s->dev, G, P, E, philox_seed, (uint64_t)trial, alpha, out->d_prim, out->d_pos,
                      d_status);
   HIP_TRY(hipGetLastError());
   return MPG_OK;

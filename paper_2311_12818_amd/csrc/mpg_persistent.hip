@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_finish_persist(DevScene S, WalkParams P
 // Seed sampling of one length bucket (same queue scheme, third head): every
 // chain of a bucket traces the same number of deduction rays.
 template <int N>
-__global__ void __launch_bounds__(256) k_seeds_persist(DevScene S, DevGuide G, int has_guide, WalkParams P,
+__global__ void __launch_bounds__(256) k_seeds_persist(DevScene S, DevGuide G, WalkParams P,
                                                        EpView E, uint64_t seed, uint64_t trial, float alpha,
                                                        int32_t* prim_out, float* pos_out, int8_t* st, int* ctr,
                                                        const int* perm) {
@@ -319,7 +319,9 @@ __global__ void __launch_bounds__(256) k_seeds_persist(DevScene S, DevGuide G, i
   const int start = ctr[CTR_OFF + N];
   const int end = ctr[CTR_OFF + N + 1];
   const int lane = threadIdx.x & 63;
-  const DevGuide* g = has_guide ? &G : nullptr;
+  // always the argument's address (no guide: a zeroed DevGuide); a pointer
+  // that may be null would make the compiler copy G to private memory
+  const DevGuide* g = &G;
   for (;;) {
     int base = next_batch(&ctr[CTR_HEAD3 + N - 1]);
     if (start + base >= end) break;
@@ -381,7 +383,7 @@ static refill_kernel_t refill_kernel(int n) {
     default: return k_walk_refill<8>;
   }
 }
-typedef void (*seeds_kernel_t)(DevScene, DevGuide, int, WalkParams, EpView, uint64_t, uint64_t, float, int32_t*,
+typedef void (*seeds_kernel_t)(DevScene, DevGuide, WalkParams, EpView, uint64_t, uint64_t, float, int32_t*,
                                float*, int8_t*, int*, const int*);
 static seeds_kernel_t seeds_kernel(int n) {
   switch (n) {
@@ -516,7 +518,7 @@ static int launch_order(uint32_t length_order, int max_len, int order[KMAX]) {
   return n_order;
 }
 
-mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P, int waves,
+mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, const WalkParams& P, int waves,
                             int bucketing, uint32_t length_order, const EpView& E, uint64_t seed, uint32_t trial,
                             float alpha, int32_t* prim_out, float* pos_out, int8_t* status, mpg_workspace* ws,
                             hipStream_t stream) {
@@ -540,7 +542,7 @@ mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, int has_guide
     const int n = order[j], q = j % MPG_WORKERS;
     seeds_kernel_t k = seeds_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, has_guide, P, E, seed,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, P, E, seed,
                        (uint64_t)trial, alpha, prim_out, pos_out, status, ctr, (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }

@@ -59,7 +59,7 @@ __device__ __forceinline__ void inv_one(const DevScene& S, const DevGuide* G, co
   if (io.truncated) io.truncated[c] = trunc ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E,
+__global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, WalkParams P, EpView E,
                                                   InvIO io) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   Stack stk = lane_stack(P.depth);
@@ -71,7 +71,9 @@ __global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, int ha
     if (io.truncated) io.truncated[c] = 0;
     return;
   }
-  const DevGuide* g = has_guide ? &G : nullptr;
+  // always the argument's address (no guide: a zeroed DevGuide); a pointer
+  // that may be null would make the compiler copy G to private memory
+  const DevGuide* g = &G;
   switch (n) {
     case 1: inv_one<1>(S, g, P, E, io, c, stk); break;
     case 2: inv_one<2>(S, g, P, E, io, c, stk); break;
@@ -107,10 +109,12 @@ __global__ void __launch_bounds__(256) k_inv_classify(EpView E, InvIO io, int8_t
 }
 
 template <int N>
-__global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, int has_guide, WalkParams P, EpView E,
+__global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, WalkParams P, EpView E,
                                                     InvIO io, int* ctr, const int* perm) {
   Stack stk = lane_stack(P.depth);
-  const DevGuide* g = has_guide ? &G : nullptr;
+  // always the argument's address (no guide: a zeroed DevGuide); a pointer
+  // that may be null would make the compiler copy G to private memory
+  const DevGuide* g = &G;
   const size_t NN = E.N;
   const int start = ctr[CTR_OFF + N];
   const int count = ctr[CTR_HIST + N];
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, int 
   }
 }
 
-typedef void (*inv_kernel_t)(DevScene, DevGuide, int, WalkParams, EpView, InvIO, int*, const int*);
+typedef void (*inv_kernel_t)(DevScene, DevGuide, WalkParams, EpView, InvIO, int*, const int*);
 static inv_kernel_t inv_refill_kernel(int n) {
   switch (n) {
     case 1: return k_inv_refill<1>;
@@ -234,7 +238,7 @@ static inv_kernel_t inv_refill_kernel(int n) {
   }
 }
 
-static mpg_status inv_persistent(const mpg_scene* s, const DevGuide& G, int has_guide, const WalkParams& P,
+static mpg_status inv_persistent(const mpg_scene* s, const DevGuide& G, const WalkParams& P,
                                  int waves, const EpView& E, const InvIO& io, mpg_workspace* ws, hipStream_t stream) {
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
@@ -248,7 +252,7 @@ static mpg_status inv_persistent(const mpg_scene* s, const DevGuide& G, int has_
   for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     inv_kernel_t k = inv_refill_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, has_guide, P, E, io, ws->counters,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, P, E, io, ws->counters,
                        (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }
@@ -281,12 +285,12 @@ extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, 
   io.max_trials = max_trials; io.repeats = repeats; io.seed = philox_seed; io.alpha = alpha;
   if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
     if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: workspace too small");
-    return inv_persistent(s, G, g ? 1 : 0, P, waves, E, io, ws, (hipStream_t)stream);
+    return inv_persistent(s, G, P, waves, E, io, ws, (hipStream_t)stream);
   }
   int threads = 64 * waves;
   size_t lds = (size_t)waves * P.depth * 64 * 4;
   hipLaunchKernelGGL(k_inv_prob, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
-                     s->dev, G, g ? 1 : 0, P, E, io);
+                     s->dev, G, P, E, io);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }
