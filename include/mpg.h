@@ -116,7 +116,8 @@ typedef struct {
 typedef struct mpg_scene mpg_scene;
 
 /* Builds the device scene on the current device: uploads geometry, builds a
- * binned-SAH BVH (64-byte two-child nodes) and per-object area tables.
+ * binned-SAH BVH (collapsed into 4-wide 128-byte nodes) and per-object
+ * area tables.
  * Allocates device memory; synchronous. */
 mpg_status mpg_scene_create(const mpg_scene_desc* desc, mpg_scene** out);
 void mpg_scene_destroy(mpg_scene* scene);

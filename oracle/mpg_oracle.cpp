@@ -797,26 +797,33 @@ struct Guide {
   std::vector<double> chol;    // [cells][comps][3]  L00, L10, L11
 };
 
-// Cell of x_D.  The cell is an integer decided by floating point, so it is
-// taken in the precision of the GPU kernel (FP32, same operation order) to
-// make the two sides agree exactly.
-static int guide_cell(const Guide& g, const V3d& x) {
+// Cell of a point on the regular res^3 grid over [lo, hi] (the spatial
+// structure of the guide, Sec. 5.6): floor((x - lo) / (hi - lo) res) per axis
+// in FP64, clamped to the grid.  Points within rounding of a cell face may
+// land in the neighbouring cell on an FP32 implementation.
+static int grid_cell(const double* lo, const double* hi, int res, const double* x) {
   int idx[3];
   for (int a = 0; a < 3; ++a) {
-    float lo = (float)g.lo[a], hi = (float)g.hi[a];
-    float f = ((float)x[a] - lo) / (hi - lo) * (float)g.res;
+    double f = (x[a] - lo[a]) / (hi[a] - lo[a]) * (double)res;
     if (!(f == f)) return -1;
-    int k = (int)std::floor(f);
-    idx[a] = std::min(std::max(k, 0), g.res - 1);
+    double k = std::floor(f);
+    idx[a] = (int)std::min(std::max(k, 0.0), (double)(res - 1));
   }
-  return (idx[2] * g.res + idx[1]) * g.res + idx[0];
+  return (idx[2] * res + idx[1]) * res + idx[0];
+}
+
+static int guide_cell(const Guide& g, const V3d& x) {
+  double p[3] = {x.x, x.y, x.z};
+  return grid_cell(g.lo, g.hi, g.res, p);
 }
 
 // p_0 (Sec. 5.4).  obj1 >= 0: x_1 uniform by area on that object;
 // obj1 == -1: uniform by area over all specular objects; for an analytic
 // sphere the point is uniform over the cap visible from x_D.  obj1 == -2:
-// the direction-based initialization (Sec. 7, "Initialization"): w_D uniform
-// in the cone of directions about n_D with cos(half-angle) = cone_cos.
+// the direction-based initialization (Sec. 6.4, "Initialization": w_D uniform
+// on the hemisphere about n_D, cone_cos = 0), here restricted to the cone
+// with cos(half-angle) = cone_cos when that cone contains every admissible
+// first direction of the workload.
 static bool sample_p0_point(const Scene& s, const Params& p, int obj1, const V3d& xD, const V3d& nD, double u1,
                             double u2, double u3, V3d* pt) {
   if (obj1 == -2) {
@@ -1041,17 +1048,10 @@ static void em_cell(const EMParams& ep, const std::vector<int>& idx, const float
   *valid = 1;
 }
 
-// Cell of a training sample, decided in FP32 like the GPU kernel (see guide_cell).
+// Cell of a training sample: its x_D on the guide's grid (grid_cell, FP64).
 static int em_cell_index(const EMParams& ep, const float* r) {
-  int idx[3];
-  for (int a = 0; a < 3; ++a) {
-    float lo = (float)ep.lo[a], hi = (float)ep.hi[a];
-    float f = (r[a] - lo) / (hi - lo) * (float)ep.res;
-    if (!(f == f)) return -1;
-    int k = (int)std::floor(f);
-    idx[a] = std::min(std::max(k, 0), ep.res - 1);
-  }
-  return (idx[2] * ep.res + idx[1]) * ep.res + idx[0];
+  double p[3] = {(double)r[0], (double)r[1], (double)r[2]};
+  return grid_cell(ep.lo, ep.hi, ep.res, p);
 }
 
 // ---------------------------------------------------------------------------

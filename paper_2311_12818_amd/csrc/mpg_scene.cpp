@@ -1,4 +1,5 @@
-// Host-side scene preparation: binned-SAH BVH with two-child 64-byte nodes,
+// Host-side scene preparation: binned-SAH binary BVH collapsed into 4-wide
+// 128-byte nodes (child boxes in structure-of-arrays order),
 // per-object area prefix sums for p_0, object xy bounds.
 #include "mpg_scene.h"
 

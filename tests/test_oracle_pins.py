@@ -631,8 +631,9 @@ def test_em_cells_and_min_samples(oracle_lib):
 
 
 def test_newton_converges_quadratically_on_the_smooth_mirror(oracle_lib):
-    # Newton's method on the constraints (Sec. 4) converges quadratically near
-    # a solution of a smooth manifold: for accepted full steps the residual
+    # Newton's method on the constraints converges quadratically near a
+    # solution of a smooth manifold (the footnote on convergence basins in
+    # Sec. 5.2): for accepted full steps the residual
     # obeys |C_{k+1}| <= c |C_k|^2.  The walk is re-run with max_iter = k to
     # read the chain after k trials.  A Jacobian that is off (a dropped term,
     # a transposed block) still converges, but only linearly, which puts the
