@@ -128,14 +128,23 @@ mpg_status mpg_scene_stats(const mpg_scene* scene, int32_t* n_nodes, int32_t* ma
  * parameters of manifold_walk_adjoint (Sec. 5.2): d_theta is device float
  * [n_params], n_params = 2 * sum of n_sines over the scene's height fields,
  * amplitude then phase per sine in height-field order.  Height-field
- * vertices and normals are recomputed (FP64 evaluation of the sine sum,
- * stored in FP32), the BVH keeps its topology and every box is refitted to
- * the triangles under it, and the per-object area tables used by p_0 and the
- * scene top used by guided seeds are recomputed.  Synchronizes hip_stream
- * (it reads theta back to validate it and the new scene top); no other work
- * on this scene may be in flight.  Errors: n_params differs from the scene's
- * count, NULL theta, non-finite theta. */
+ * vertices and normals are recomputed (FP32 evaluation of the sine sum), the
+ * BVH keeps its topology and every box is refitted to the triangles under
+ * it, and the per-object area tables used by p_0 and the scene top used by
+ * guided seeds are recomputed on the device.  Stream ordered with no host
+ * synchronization and no allocation, so it may be captured into a HIP graph
+ * together with the walks that follow; work on this scene queued on other
+ * streams must not overlap it.  Host-detected errors: n_params differs from
+ * the scene's count, NULL theta.  A non-finite theta is detected on the
+ * device: the scene is left unchanged and the scene's error word (read with
+ * mpg_scene_params_error) becomes MPG_ERR_INVALID_ARG; a valid update resets
+ * it to MPG_OK. */
 mpg_status mpg_scene_set_params(mpg_scene* scene, const float* d_theta, int32_t n_params, void* hip_stream);
+/* Copies the scene's error word of the last mpg_scene_set_params (MPG_OK
+ * initially) into d_out[0] (device int32), in stream order on hip_stream
+ * (a device-to-device copy; no host synchronization).  Errors: NULL scene or
+ * d_out. */
+mpg_status mpg_scene_params_error(const mpg_scene* scene, int32_t* d_out, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batches                                                                    */
@@ -292,7 +301,8 @@ mpg_status mpg_walk_count(const mpg_scene* scene, const mpg_walk_params* params,
  * reaches the target again (same objects, every vertex within match_rel L);
  * K = that trial count, or max_trials when none matched (d_truncated = 1).
  * d_inv_prob = mean_r K_r / P(n) with P(n) = 1 (n is given), d_trials =
- * sum_r K_r.  Other targets get 0.  d_truncated may be NULL.  With
+ * sum_r K_r.  Other targets, and targets longer than params->max_len (which
+ * bounds the per-length kernels launched), get 0.  d_truncated may be NULL.  With
  * params->form == MPG_FORM_PERSISTENT and bucketing on, the targets are
  * grouped by length in ws (capacity >= N) and every lane of one persistent
  * kernel per length takes the next target as soon as its trials end; the

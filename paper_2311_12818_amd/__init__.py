@@ -24,6 +24,7 @@ CONVERGED, MAX_ITER, SINGULAR, SIDE_INVALID, OCCLUDED, SEED_INVALID, FP64_REJECT
 STATUS_NAMES = ["converged", "max_iter", "singular", "side_invalid", "occluded", "seed_invalid", "fp64_reject",
                 "bad_input"]
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
+OK, ERR_INVALID_ARG, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 P0_ANY_OBJECT, P0_DIRECTION = -1, -2
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
         L.mpg_scene_create.argtypes = [C.POINTER(mpg_scene_desc), C.POINTER(P)]
         L.mpg_scene_destroy.argtypes = [P]
         L.mpg_scene_set_params.argtypes = [P, P, I32, P]
+        L.mpg_scene_params_error.argtypes = [P, P, P]
         L.mpg_scene_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
         L.mpg_walk_params_default.argtypes = [F32, C.POINTER(mpg_walk_params)]
         L.mpg_workspace_create.argtypes = [I32, C.POINTER(P)]
@@ -114,7 +116,8 @@ def lib():
         for name in ["mpg_scene_create", "mpg_scene_stats", "mpg_walk_params_default", "mpg_workspace_create",
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
                      "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
-                     "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples", "mpg_scene_set_params"]:
+                     "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples", "mpg_scene_set_params",
+                     "mpg_scene_params_error"]:
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -190,6 +193,17 @@ class Scene:
         torch = _torch()
         th = theta.detach().to(device="cuda", dtype=torch.float32).contiguous()
         _check(lib().mpg_scene_set_params(self.h, th.data_ptr(), int(th.numel()), _stream()), "mpg_scene_set_params")
+        self._theta_keep = th   # stays alive until the queued update has read it
+
+    def params_error(self):
+        """The scene's device error word after the last set_params (int32
+        device tensor of one element, read in stream order): 0 when theta was
+        valid, MPG_ERR_INVALID_ARG when it held a non-finite value and the
+        scene was left unchanged."""
+        torch = _torch()
+        out = torch.empty(1, dtype=torch.int32, device="cuda")
+        _check(lib().mpg_scene_params_error(self.h, out.data_ptr(), _stream()), "mpg_scene_params_error")
+        return out
 
     def stats(self):
         a, b, c = I32(), I32(), I32()

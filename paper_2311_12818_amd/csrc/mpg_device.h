@@ -163,12 +163,12 @@ struct DevScene {
   const int2* obj_info;     // [n_objects] (material, ior as float bits)
   const float4* spheres;    // [n_spheres] centre, radius
   const int* sphere_obj;    // [n_spheres]
-  const double* cdf;        // area prefix sums, one run per object and one over all objects
+  const float* cdf;         // area prefix sums, one run per object and one over all objects
   const int* cdf_prim;
   const int2* cdf_range;    // [n_objects + 1] (start, count)
   const float4* obj_bounds; // [n_objects] (lo_x, lo_y, hi_x, hi_y)
+  const float* zmax;        // top of the geometry (device word, follows surface-parameter updates)
   int n_tris, n_spheres, n_objects, n_nodes;
-  float zmax;
 };
 
 struct DevGuide {
@@ -1062,10 +1062,10 @@ __device__ __forceinline__ bool p0_point(const DevScene& S, const WalkParams& P,
   if (key > S.n_objects) return false;
   int2 rg = S.cdf_range[key];
   if (rg.y <= 0) return false;
-  const double* cdf = S.cdf + rg.x;
-  double total = cdf[rg.y - 1];
-  if (!(total > 0.0)) return false;
-  double target = (double)u1 * total;
+  const float* cdf = S.cdf + rg.x;
+  float total = cdf[rg.y - 1];
+  if (!(total > 0.0f)) return false;
+  float target = u1 * total;
   int lo = 0, hi = rg.y;  // first index with cdf > target
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
@@ -1120,10 +1120,11 @@ __device__ __forceinline__ bool guided_point(const DevScene& S, const DevGuide& 
     float4 bd = S.obj_bounds[G.target_obj];
     if (px < bd.x || px > bd.z || py < bd.y || py > bd.w) continue;
     Hit h;
-    f3 o = {px, py, S.zmax + 1.0f};
+    const float top = *S.zmax + 1.0f;
+    f3 o = {px, py, top};
     trace(S, o, f3{0.0f, 0.0f, -1.0f}, PRIM_NONE, 0.0f, h, stk);
     if (h.prim == PRIM_NONE) return false;
-    pt = {px, py, S.zmax + 1.0f - h.t};
+    pt = {px, py, top - h.t};
     return true;
   }
   return false;

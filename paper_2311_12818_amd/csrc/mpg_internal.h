@@ -50,6 +50,7 @@ struct mpg_scene {
   float pad = 0.0f;
   float zmax_static = -INFINITY;
   uint32_t* zmax_bits = nullptr;
+  int32_t* param_err = nullptr;  // MPG_OK, or MPG_ERR_INVALID_ARG after a non-finite theta
 };
 
 // Lower bound on resident wavefronts per SIMD for the lane-refill kernels of
@@ -72,6 +73,7 @@ struct mpg_workspace {
   int32_t* counters = nullptr; // [MPG_WS_COUNTERS] histogram / offsets / queue heads / batch box
   int32_t* cells = nullptr;    // [2 * 8 * MPG_CELLS] spatial-cell counts and cursors
   int32_t* aux = nullptr;      // [cap] scratch (sample cell ids, sorted indices)
+  int single_stream = 0;       // 1: every per-length kernel on the caller's stream (no internal streams)
   std::vector<void*> allocs;
 };
 

@@ -149,7 +149,8 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     sph[k] = make_float4(d->spheres[4 * k], d->spheres[4 * k + 1], d->spheres[4 * k + 2], d->spheres[4 * k + 3]);
     zmax = std::max(zmax, d->spheres[4 * k + 2] + d->spheres[4 * k + 3]);
   }
-  // area prefix sums (double, input order) per object and over all objects
+  // area prefix sums per object and over all objects (input order), summed in
+  // FP64 on the host and stored as their FP32 roundings
   int O = d->n_objects;
   std::vector<std::vector<double>> cd(O + 1);
   std::vector<std::vector<int>> cp(O + 1);
@@ -184,15 +185,14 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     ob[o].x = std::min(ob[o].x, sph[k].x - sph[k].w); ob[o].y = std::min(ob[o].y, sph[k].y - sph[k].w);
     ob[o].z = std::max(ob[o].z, sph[k].x + sph[k].w); ob[o].w = std::max(ob[o].w, sph[k].y + sph[k].w);
   }
-  std::vector<double> cdf;
+  std::vector<float> cdf;
   std::vector<int> cprim;
   std::vector<int2> crange(O + 1);
   for (int k = 0; k <= O; ++k) {
     crange[k] = make_int2((int)cdf.size(), (int)cd[k].size());
-    cdf.insert(cdf.end(), cd[k].begin(), cd[k].end());
+    for (double c : cd[k]) cdf.push_back((float)c);
     cprim.insert(cprim.end(), cp[k].begin(), cp[k].end());
   }
-  D.zmax = zmax;
   if ((e = upload(s->allocs, &D.nodes, (const float4*)nodes.data(), nodes.size() / 4)) != hipSuccess) return bail(e, "nodes");
   if ((e = upload(s->allocs, &D.tri_v, tv.data(), tv.size())) != hipSuccess) return bail(e, "triangles");
   if ((e = upload(s->allocs, &D.tri_idx, ti.data(), ti.size())) != hipSuccess) return bail(e, "triangle ids");
@@ -210,6 +210,13 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
   if ((e = upload(s->allocs, &s->order, order.data(), order.size())) != hipSuccess) return bail(e, "leaf order");
   if ((e = upload(s->allocs, &s->ranges, ranges.data(), ranges.size())) != hipSuccess) return bail(e, "node ranges");
   if ((e = dalloc(s->allocs, &s->zmax_bits, 1)) != hipSuccess) return bail(e, "scratch");
+  if ((e = upload(s->allocs, &D.zmax, &zmax, 1)) != hipSuccess) return bail(e, "scene top");
+  {
+    const int32_t ok = MPG_OK;
+    const int32_t* pe = nullptr;
+    if ((e = upload(s->allocs, &pe, &ok, 1)) != hipSuccess) return bail(e, "error word");
+    s->param_err = (int32_t*)pe;
+  }
   *out = s;
   return MPG_OK;
 }

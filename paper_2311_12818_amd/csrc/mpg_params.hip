@@ -13,54 +13,79 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
   uint32_t u = __float_as_uint(f);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-inline float from_ordered_bits(uint32_t u) {
+__device__ __forceinline__ float from_ordered_bits(uint32_t u) {
   uint32_t v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
-  float f;
-  std::memcpy(&f, &v, 4);
-  return f;
+  return __uint_as_float(v);
 }
 
-__global__ void k_set_word(uint32_t* p, uint32_t v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
-}
-
-// amplitude and phase of every sine of every height field
-__global__ void k_hf_params(DevHF* hf, int n_hf, const float* theta) {
-  int h = blockIdx.x, k = threadIdx.x;
-  if (h >= n_hf || k >= hf[h].n_sines) return;
-  hf[h].amp[k] = theta[hf[h].param_base + 2 * k];
-  hf[h].phase[k] = theta[hf[h].param_base + 2 * k + 1];
+// Validates theta and installs it: a single workgroup checks every value;
+// when one is not finite the error word is set and the scene is left as it
+// was (every later kernel of the update reads the word and does nothing).
+// Otherwise the amplitude and phase of every sine are stored and the scene
+// top accumulator is reset.
+__global__ void __launch_bounds__(256) k_hf_params(DevHF* hf, int n_hf, const float* theta, int n_params,
+                                                   int32_t* err, uint32_t* zmax_bits) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_params; i += blockDim.x)
+    if (!isfinite(theta[i])) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *err = bad ? MPG_ERR_INVALID_ARG : MPG_OK;
+    if (!bad) *zmax_bits = 0u;
+  }
+  if (bad) return;
+  for (int h = 0; h < n_hf; ++h)
+    for (int k = threadIdx.x; k < hf[h].n_sines; k += blockDim.x) {
+      hf[h].amp[k] = theta[hf[h].param_base + 2 * k];
+      hf[h].phase[k] = theta[hf[h].param_base + 2 * k + 1];
+    }
 }
 
 // vertices of one height field: z = z0 + sum a sin(f (cos psi x + sin psi y) + phi),
-// n = normalize(-dz/dx, -dz/dy, 1), evaluated in FP64 and stored in FP32
-__global__ void k_hf_vertices(const DevHF* hf, int h, float z0, float4* vpos, float4* vnrm, uint32_t* zmax_bits) {
+// n = normalize(-dz/dx, -dz/dy, 1), in FP32
+__global__ void k_hf_vertices(const DevHF* hf, int h, float z0, float4* vpos, float4* vnrm, uint32_t* zmax_bits,
+                              const int32_t* err) {
+  if (*err != MPG_OK) return;
   const DevHF& H = hf[h];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_verts) return;
   int v = H.first_vert + i;
   float4 p = vpos[v];
-  double x = p.x, y = p.y;
-  double z = z0, hx = 0.0, hy = 0.0;
+  float z = 0.0f, hx = 0.0f, hy = 0.0f;
   for (int k = 0; k < H.n_sines; ++k) {
-    double cp = cos((double)H.psi[k]), sp = sin((double)H.psi[k]);
-    double arg = (double)H.freq[k] * (cp * x + sp * y) + (double)H.phase[k];
-    z += (double)H.amp[k] * sin(arg);
-    double c = (double)H.amp[k] * (double)H.freq[k] * cos(arg);
+    float sp, cp;
+    sincosf(H.psi[k], &sp, &cp);
+    float arg = H.freq[k] * (cp * p.x + sp * p.y) + H.phase[k];
+    float sa, ca;
+    sincosf(arg, &sa, &ca);
+    z += H.amp[k] * sa;
+    float c = H.amp[k] * H.freq[k] * ca;
     hx += c * cp;
     hy += c * sp;
   }
-  double il = 1.0 / sqrt(hx * hx + hy * hy + 1.0);
-  float nx = (float)(-hx * il), ny = (float)(-hy * il), nz = (float)il;
+  float il = rsqrtf(hx * hx + hy * hy + 1.0f);
+  float nx = -hx * il, ny = -hy * il, nz = il;
   float l = sqrtf(nx * nx + ny * ny + nz * nz);
-  float zf = (float)z;
+  float zf = z0 + z;
   vpos[v] = make_float4(p.x, p.y, zf, 0.f);
   vnrm[v] = make_float4(nx / l, ny / l, nz / l, 0.f);
   atomicMax(zmax_bits, ordered_bits(zf));
 }
 
+// scene top used to lift guided seeds: the static geometry's top and the
+// highest height-field vertex
+__global__ void k_zmax(const uint32_t* zmax_bits, float zmax_static, float* zmax, const int32_t* err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *err != MPG_OK) return;
+  uint32_t b = *zmax_bits;
+  *zmax = b == 0u ? zmax_static : fmaxf(zmax_static, from_ordered_bits(b));
+}
+
 // triangle copies in BVH leaf order (first vertex carries the primitive id)
-__global__ void k_tri_copies(int n_tris, const int32_t* order, const int4* tri_idx, const float4* vpos, float4* tri_v) {
+__global__ void k_tri_copies(int n_tris, const int32_t* order, const int4* tri_idx, const float4* vpos, float4* tri_v,
+                             const int32_t* err) {
+  if (*err != MPG_OK) return;
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tris) return;
   int t = order[k];
@@ -84,7 +109,8 @@ __device__ __forceinline__ float wave_max(float v) {
 // box of the triangles of its range, padded like the builder's (an empty
 // child keeps its box at +infinity)
 __global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* ranges, const float4* tri_v, float* nodes,
-                                               float pad) {
+                                               float pad, const int32_t* err) {
+  if (*err != MPG_OK) return;
   int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (g >= n_nodes) return;
@@ -117,30 +143,35 @@ __global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* range
   }
 }
 
-// per-object area prefix sums (one thread per run, sequential in FP64, the
-// builder's order)
+// per-object area prefix sums in FP32 (one thread per run, the builder's
+// order), accumulated with Kahan's compensated summation so that every
+// prefix is the FP32 rounding of the exact running sum to within an ulp or two
 __global__ void k_area_cdf(int n_runs, const int2* range, const int* cdf_prim, const int4* tri_idx,
-                           const float4* vpos, const float4* spheres, double* cdf) {
+                           const float4* vpos, const float4* spheres, float* cdf, const int32_t* err) {
+  if (*err != MPG_OK) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_runs) return;
   int2 rg = range[r];
-  double acc = 0.0;
+  float acc = 0.0f, comp = 0.0f;
   for (int i = 0; i < rg.y; ++i) {
     int p = cdf_prim[rg.x + i];
-    double area;
+    float area;
     if (p >= 0) {
       int4 id = tri_idx[p];
       float4 a = vpos[id.x], b = vpos[id.y], c = vpos[id.z];
-      double e1[3] = {(double)b.x - a.x, (double)b.y - a.y, (double)b.z - a.z};
-      double e2[3] = {(double)c.x - a.x, (double)c.y - a.y, (double)c.z - a.z};
-      double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2];
-      double cz = e1[0] * e2[1] - e1[1] * e2[0];
-      area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+      float e1[3] = {b.x - a.x, b.y - a.y, b.z - a.z};
+      float e2[3] = {c.x - a.x, c.y - a.y, c.z - a.z};
+      float cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2];
+      float cz = e1[0] * e2[1] - e1[1] * e2[0];
+      area = 0.5f * sqrtf(cx * cx + cy * cy + cz * cz);
     } else {
-      double rad = spheres[-1 - p].w;
-      area = 4.0 * M_PI * rad * rad;
+      float rad = spheres[-1 - p].w;
+      area = 4.0f * (float)M_PI * rad * rad;
     }
-    acc += area;
+    float y = area - comp;
+    float t = acc + y;
+    comp = (t - acc) - y;
+    acc = t;
     cdf[rg.x + i] = acc;
   }
 }
@@ -154,43 +185,37 @@ extern "C" mpg_status mpg_scene_set_params(mpg_scene* s, const float* d_theta, i
   if (n_params == 0) return MPG_OK;
   if (!d_theta) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_set_params: NULL theta");
   hipStream_t stream = (hipStream_t)stream_;
-  std::vector<float> th(n_params);
-  HIP_TRY(hipMemcpyAsync(th.data(), d_theta, n_params * sizeof(float), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  for (float v : th)
-    if (!std::isfinite(v)) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_set_params: non-finite theta");
   DevScene& D = s->dev;
   const int n_hf = (int)s->hfs.size();
-  hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, stream, s->zmax_bits, 0u);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_hf_params, dim3(n_hf), dim3(64), 0, stream, (DevHF*)s->dev_hf, n_hf, d_theta);
+  hipLaunchKernelGGL(k_hf_params, dim3(1), dim3(256), 0, stream, (DevHF*)s->dev_hf, n_hf, d_theta, n_params,
+                     s->param_err, s->zmax_bits);
   HIP_TRY(hipGetLastError());
   for (int h = 0; h < n_hf; ++h) {
     int nv = s->hfs[h].res * s->hfs[h].res;
     hipLaunchKernelGGL(k_hf_vertices, dim3((nv + 255) / 256), dim3(256), 0, stream, s->dev_hf, h, s->hfs[h].z0,
-                       (float4*)D.vpos, (float4*)D.vnrm, s->zmax_bits);
+                       (float4*)D.vpos, (float4*)D.vnrm, s->zmax_bits, (const int32_t*)s->param_err);
     HIP_TRY(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_zmax, dim3(1), dim3(64), 0, stream, (const uint32_t*)s->zmax_bits, s->zmax_static,
+                     (float*)D.zmax, (const int32_t*)s->param_err);
+  HIP_TRY(hipGetLastError());
   if (s->n_tris > 0) {
     hipLaunchKernelGGL(k_tri_copies, dim3((s->n_tris + 255) / 256), dim3(256), 0, stream, s->n_tris, s->order,
-                       D.tri_idx, D.vpos, (float4*)D.tri_v);
+                       D.tri_idx, D.vpos, (float4*)D.tri_v, (const int32_t*)s->param_err);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_refit, dim3((s->n_nodes + 3) / 4), dim3(256), 0, stream, s->n_nodes, s->ranges, D.tri_v,
-                       (float*)D.nodes, s->pad);
+                       (float*)D.nodes, s->pad, (const int32_t*)s->param_err);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_area_cdf, dim3((s->n_objects + 1 + 63) / 64), dim3(64), 0, stream, s->n_objects + 1, D.cdf_range, D.cdf_prim, D.tri_idx,
-                     D.vpos, D.spheres, (double*)D.cdf);
+  hipLaunchKernelGGL(k_area_cdf, dim3((s->n_objects + 1 + 63) / 64), dim3(64), 0, stream, s->n_objects + 1,
+                     D.cdf_range, D.cdf_prim, D.tri_idx, D.vpos, D.spheres, (float*)D.cdf,
+                     (const int32_t*)s->param_err);
   HIP_TRY(hipGetLastError());
-  uint32_t bits = 0;
-  HIP_TRY(hipMemcpyAsync(&bits, s->zmax_bits, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  D.zmax = bits == 0 ? s->zmax_static : std::max(s->zmax_static, from_ordered_bits(bits));
-  for (int h = 0; h < n_hf; ++h) {
-    mpg_heightfield& H = s->hfs[h];
-    int base = 0;
-    for (int k = 0; k < h; ++k) base += 2 * s->hfs[k].n_sines;
-    for (int k = 0; k < H.n_sines; ++k) { H.amp[k] = th[base + 2 * k]; H.phase[k] = th[base + 2 * k + 1]; }
-  }
+  return MPG_OK;
+}
+
+extern "C" mpg_status mpg_scene_params_error(const mpg_scene* s, int32_t* d_out, void* stream) {
+  if (!s || !d_out) return fail(MPG_ERR_INVALID_ARG, "mpg_scene_params_error: NULL scene or output");
+  HIP_TRY(hipMemcpyAsync(d_out, s->param_err, sizeof(int32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return MPG_OK;
 }

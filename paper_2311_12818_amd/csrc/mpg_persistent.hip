@@ -581,8 +581,12 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
   mpg_status bst = bucket_chains(bucketing, max_len, 1, E, io, ws, stream);
   if (bst != MPG_OK) return bst;
   hipStream_t wk[MPG_WORKERS];
-  mpg_status st = workers_fork(stream, wk);
-  if (st != MPG_OK) return st;
+  if (ws->single_stream) {
+    for (int q = 0; q < MPG_WORKERS; ++q) wk[q] = stream;
+  } else {
+    mpg_status st = workers_fork(stream, wk);
+    if (st != MPG_OK) return st;
+  }
   // lengths dealt round robin to the workers in launch order (length_order,
   // else longest first; lengths above max_len left out); every finish pass
   // is queued after all walks, on its walk's worker.  A finish pass launched
@@ -611,5 +615,5 @@ mpg_status walk_persistent(const mpg_scene* s, const WalkParams& P, int waves, i
     hipLaunchKernelGGL(f, dim3(fgrid), dim3(threads), lds, wk[q], s->dev, P, E, io, ctr, (const int*)ws->perm);
     HIP_TRY(hipGetLastError());
   }
-  return workers_join(stream);
+  return ws->single_stream ? MPG_OK : workers_join(stream);
 }

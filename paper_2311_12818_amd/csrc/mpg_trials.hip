@@ -12,6 +12,7 @@ struct InvIO {
   float* inv_prob;
   uint8_t* truncated;
   int max_trials, repeats;
+  int max_len;  // targets longer than this are not estimated (zero outputs)
   uint64_t seed;
   float alpha;
 };
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(256) k_inv_prob(DevScene S, DevGuide G, WalkPa
   Stack stk = lane_stack(P.depth);
   if (c >= E.N) return;
   int n = E.len[c];
-  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > KMAX || io.repeats < 1 || io.max_trials < 1) {
+  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > io.max_len || io.repeats < 1 || io.max_trials < 1) {
     io.trials[c] = 0;
     io.inv_prob[c] = 0.f;
     if (io.truncated) io.truncated[c] = 0;
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(256) k_inv_classify(EpView E, InvIO io, int8_t
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= E.N) return;
   int n = E.len[c];
-  bool target = io.tstatus[c] == ST_CONVERGED && n >= 1 && n <= KMAX && io.repeats >= 1 && io.max_trials >= 1;
+  bool target = io.tstatus[c] == ST_CONVERGED && n >= 1 && n <= io.max_len && io.repeats >= 1 && io.max_trials >= 1;
   cls[c] = (int8_t)(target ? n : 0);
   if (!target) {
     io.trials[c] = 0;
@@ -249,7 +250,8 @@ static mpg_status inv_persistent(const mpg_scene* s, const DevGuide& G, const Wa
   if (st != MPG_OK) return st;
   hipStream_t wk[MPG_WORKERS];
   if ((st = workers_fork(stream, wk)) != MPG_OK) return st;
-  for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+  // only the lengths the call may hold (1..max_len), longest first
+  for (int n = io.max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
     inv_kernel_t k = inv_refill_kernel(n);
     int grid = resident_blocks((const void*)k, threads, lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, G, P, E, io, ws->counters,
@@ -283,6 +285,7 @@ extern "C" mpg_status estimate_inv_prob(const mpg_scene* s, const mpg_guide* g, 
   io.tprim = target->d_prim; io.tpos = target->d_pos; io.tstatus = d_target_status;
   io.trials = d_trials; io.inv_prob = d_inv_prob; io.truncated = d_truncated;
   io.max_trials = max_trials; io.repeats = repeats; io.seed = philox_seed; io.alpha = alpha;
+  io.max_len = std::min(std::max(p->max_len, 1), KMAX);
   if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
     if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob: workspace too small");
     return inv_persistent(s, G, P, waves, E, io, ws, (hipStream_t)stream);

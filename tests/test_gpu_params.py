@@ -92,7 +92,93 @@ def test_set_params_rejects_bad_input(mpg):
     scene = M.Scene(W.slab_stack_scene())
     with pytest.raises(M.MPGError):
         scene.set_params(torch.zeros(31))
-    with pytest.raises(M.MPGError):
-        scene.set_params(torch.full((32,), float("nan")))
     sph = M.Scene(W.sphere_mirror_scene())
     sph.set_params(torch.zeros(0))   # no parameters: a no-op
+
+
+def test_set_params_non_finite_theta_leaves_the_scene_unchanged(mpg):
+    # a non-finite theta is found on the device (the call never reads theta
+    # back): the error word is set, every later kernel of the update skips,
+    # and walks on the scene are exactly those before the call
+    import torch
+    M = mpg
+    sc = W.slab_stack_scene()
+    scene = M.Scene(sc)
+    assert int(scene.params_error().item()) == 0
+    ep = W.slab_uneven_endpoints(4096, seed=23)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    before = _walk(M, scene, sc, ep, prim, pos, st)
+    bad = torch.as_tensor(W.slab_theta(sc), dtype=torch.float32)
+    bad[5] = float("nan")
+    scene.set_params(bad)
+    assert int(scene.params_error().item()) == M.ERR_INVALID_ARG
+    after = _walk(M, scene, sc, ep, prim, pos, st)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    scene.set_params(torch.as_tensor(W.slab_theta(sc), dtype=torch.float32))
+    assert int(scene.params_error().item()) == 0
+
+
+def test_captured_set_params_walk_and_adjoint_replay_bit_exact(mpg):
+    # the differentiable step (new theta -> seeds -> walk -> adjoint) is
+    # stream ordered without host synchronization, so it can be captured into
+    # one HIP graph; every replay (with other eager work between replays)
+    # must reproduce the eager step bit for bit
+    import torch
+    M = mpg
+    sc = W.slab_stack_scene()
+    th0 = W.slab_theta(sc)
+    g = np.random.default_rng(7)
+    th1 = th0.copy()
+    th1[0::2] *= g.uniform(0.7, 1.3, th1[0::2].shape)
+    theta = torch.as_tensor(th1, dtype=torch.float32).cuda()
+    n = 1 << 14
+    ep = W.slab_adjoint_endpoints(n, seed=31)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    prm = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), max_len=4)
+    prim, pos = M.empty_chains(n)
+    outs = M.walk_outputs(n)
+    r, gG = W.loss_weights(n)
+    gpos = torch.as_tensor(r).cuda()
+    ggG = torch.as_tensor(gG).cuda()
+    gxD = torch.zeros(3, n, device="cuda")
+    gxL = torch.zeros(3, n, device="cuda")
+    gth = torch.zeros(32, device="cuda")
+
+    def step():
+        scene.set_params(theta)
+        p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos))
+        M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs)
+        gth.zero_()
+        M.manifold_walk_adjoint(scene, prm, dep, prim, pos, outs["status"], grad_pos=gpos, grad_G=ggG,
+                                grad_xD=gxD, grad_xL=gxL, grad_theta=gth)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = {k: GC.to_np(v).copy() for k, v in outs.items()}
+    ref_xD, ref_xL = GC.to_np(gxD).copy(), GC.to_np(gxL).copy()
+    assert (ref["status"] == M.CONVERGED).mean() > 0.3
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        # move the scene elsewhere eagerly, clobber the outputs, then replay
+        scene.set_params(torch.as_tensor(th0, dtype=torch.float32))
+        for v in outs.values():
+            v.fill_(-1) if v.dtype != torch.float32 else v.fill_(float("nan"))
+        gxD.fill_(float("nan"))
+        gxL.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, v in outs.items():
+            assert np.array_equal(GC.to_np(v), ref[k]), (rep, k)
+        assert np.array_equal(GC.to_np(gxD), ref_xD), rep
+        assert np.array_equal(GC.to_np(gxL), ref_xL), rep
