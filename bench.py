@@ -37,8 +37,22 @@ FLOPS_PER_UNIT = {
     "vertex_residual_evals": 175,  # primitive frame, blended normal, half vector, projections
     "vertex_jacobian_evals": 540,  # + normal derivatives, 3 Jacobian blocks, block-Thomas step, back-substitution
 }
+# The same work priced at the scope estimates written before any kernel existed:
+# a ray costs 20 per box test and 40 per triangle test (25 per sphere test),
+# a vertex with Jacobian and block-Thomas step 400 (constraint + blocks 350,
+# solve 50), a residual-only vertex 60.  Reported beside the source-counted
+# prices so that either fraction can be re-derived from the counts.
+SURVEY_FLOPS_PER_UNIT = {
+    "box_tests": 20, "tri_tests": 40, "sphere_tests": 25, "rays": 0,
+    "vertex_residual_evals": 60, "vertex_jacobian_evals": 400,
+}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# Weighted EM, FP32 flops per (sample, component, iteration) from the kernel
+# source: E step (centred offset, quadratic form with the inverse covariance,
+# log-weight, exp, normalisation) about 24, M step (weighted first and second
+# moments) about 12.
+EM_FLOPS_PER_SAMPLE_COMP_ITER = 36
 
 
 def parse():
@@ -62,6 +76,10 @@ def parse():
                     help="configurations of the guided-sampling / Bernoulli-trial leg (0 = skip)")
     ap.add_argument("--adjoint-n", type=int, default=1 << 20,
                     help="chains of the forward+adjoint leg on the differentiation workload (0 = skip)")
+    ap.add_argument("--configs-leg", type=int, default=1,
+                    help="also time the sphere-mirror (4096) and icosphere (2^20) workloads in both forms")
+    ap.add_argument("--per-length", type=int, default=1,
+                    help="also time each chain length of the batch on its own (persistent form)")
     return ap.parse_args()
 
 
@@ -218,7 +236,106 @@ def guide_leg(M, W, args):
                "converged_walks_per_s": conv / (walk_ms / 1e3),
                "trial_walks_per_s": tw / (trial_ms / 1e3),
                "walks_per_s_including_trials": (ep.N + tw) / ((walk_ms + trial_ms) / 1e3)}
+    # rooflines: a trial is one guided seed draw plus one walk of the same
+    # distribution, priced at the counted work per walk of the guided batch
+    # (untimed counting walk over its first 2^18 configurations); EM at its
+    # per-(sample, component, iteration) price
+    m = min(ep.N, 1 << 18)
+    sub = M.Endpoints(W.water_endpoints(args.guide_n).subset(slice(0, m)))
+    p, q, st = M.sample_seeds(scene, sub, M.walk_params(sc.scale, max_len=1), alpha=0.5, guide=gd)
+    _, _, _, counts = M.walk_count(scene, M.walk_params(sc.scale, max_len=1), sub, p, q, st)
+    per_walk = sum(FLOPS_PER_UNIT[k] * counts[k] for k in FLOPS_PER_UNIT) / m
+    t_ach = res["trial_walks"] * per_walk / (res["trials_ms"] / 1e3) / 1e12
+    res["roofline"] = {"bound": "alu", "kernel": "k_inv_refill<1>", "achieved": t_ach, "peak": PEAK_FP32_TFLOPS,
+                       "unit": "TFLOP/s", "frac": t_ach / PEAK_FP32_TFLOPS, "flops_per_trial_walk": per_walk}
+    em_flops = train["samples"] * 8 * 30 * EM_FLOPS_PER_SAMPLE_COMP_ITER
+    e_ach = em_flops / (train["fit_guide_ms"] / 1e3) / 1e12
+    train["roofline"] = {"bound": "alu", "kernel": "fit_guide (k_em_*)", "achieved": e_ach, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": e_ach / PEAK_FP32_TFLOPS, "flops": em_flops}
     return {"workload": "water_caustic", "training": train, "guided": res}
+
+
+def configs_leg(M, W, args):
+    """The two single-shape workloads, both forms, timed with HIP events
+    (seeds + walk + FP64 pass): the analytic sphere mirror (4096 chains of
+    one reflection) and the two-refraction icosphere (2^20 chains)."""
+    import torch
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, n, max_len in (("sphere_mirror", 4096, 1), ("icosphere_tt", 1 << 20, 2)):
+        scene_fn, ep_fn = W.WORKLOADS[name]
+        sc = scene_fn()
+        scene = M.Scene(sc)
+        dep = M.Endpoints(ep_fn(n))
+        ws = M.Workspace(n)
+        prim, pos = M.empty_chains(n)
+        outs = M.walk_outputs(n)
+        res = {"chains": n}
+        for form in ("plain", "persistent"):
+            kw = dict(max_len=max_len, defer_fp64=1)
+            if form == "persistent":
+                kw.update(form=M.FORM_PERSISTENT, bucketing=1, refill=1)
+            prm = M.walk_params(sc.scale, **kw)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            reps = max(1, args.steps)
+            for rep in range(reps + 1):   # the first pass warms up
+                e[0].record(stream)
+                p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
+                M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+                M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+                e[1].record(stream)
+                torch.cuda.synchronize()
+                if rep == 0:
+                    total = 0.0
+                else:
+                    total += e[0].elapsed_time(e[1])
+            ms = total / reps
+            conv = int((outs["status"] == M.CONVERGED).sum())
+            res[form] = {"ms_per_step": ms, "converged": conv, "converged_walks_per_s": conv / (ms / 1e3),
+                         "attempted_walks_per_s": n / (ms / 1e3)}
+        out[name] = res
+    return out
+
+
+def per_length_leg(M, W, args, params, scene, ep):
+    """Each chain length of the batch walked on its own (same chains, same
+    launch knobs), timed with HIP events: converged walks/s of length k when
+    only length k runs."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    prm = params("persistent")
+    res = {}
+    for k in range(1, 9):
+        idx = np.nonzero(ep.length == k)[0]
+        if len(idx) == 0:
+            continue
+        sub = ep.subset(idx)
+        dep = M.Endpoints(sub)
+        n = sub.n
+        ws = M.Workspace(n)
+        prim, pos = M.empty_chains(n)
+        outs = M.walk_outputs(n)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        reps = max(1, args.steps // 2)
+        tot = [0.0, 0.0]
+        for rep in range(reps + 1):
+            e[0].record(stream)
+            p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
+            e[1].record(stream)
+            M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+            M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                tot[0] += e[0].elapsed_time(e[1])
+                tot[1] += e[1].elapsed_time(e[2])
+        seeds_ms, walk_ms = tot[0] / reps, tot[1] / reps
+        conv = int((outs["status"] == M.CONVERGED).sum())
+        res[str(k)] = {"chains": n, "converged": conv, "seeds_ms": seeds_ms, "walk_ms": walk_ms,
+                       "converged_walks_per_s": conv / ((seeds_ms + walk_ms) / 1e3),
+                       "walk_only_converged_walks_per_s": conv / (walk_ms / 1e3)}
+    return res
 
 
 def adjoint_leg(M, W, args, tuned_all, cone):
@@ -273,8 +390,22 @@ def adjoint_leg(M, W, args, tuned_all, cone):
     wall = (time.perf_counter() - t0) / steps
     fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
-    conv = int((outs["status"] == M.CONVERGED).sum())
-    return {"workload": "slab_adjoint", "chains": n, "converged": conv, "ms_per_step": 1e3 * wall,
+    conv_mask = (outs["status"] == M.CONVERGED).cpu().numpy()
+    conv = int(conv_mask.sum())
+    # adjoint work priced per dual-number sweep: one sweep evaluates the
+    # residual and the Jacobian of every vertex (vertex_jacobian_evals price)
+    # in value and tangent parts (x2); a chain of length n runs 2n sweeps for
+    # dG/dy, 6 for the endpoints and 8 per height field it touches (the slab
+    # tops at odd interface numbers: ceil(n / 2)), plus two block-Thomas
+    # solves priced inside the vertex price
+    import numpy as np
+    nl = ep.length[conv_mask].astype(np.int64)
+    sweeps = 2 * nl + 6 + 8 * ((nl + 1) // 2)
+    adj_flops = float(np.sum(sweeps * nl * 2 * FLOPS_PER_UNIT["vertex_jacobian_evals"]))
+    a_ach = adj_flops / (adj_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_adjoint_persist<n>", "achieved": a_ach, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": a_ach / PEAK_FP32_TFLOPS, "flops": adj_flops}
+    return {"workload": "slab_adjoint", "chains": n, "converged": conv, "ms_per_step": 1e3 * wall, "roofline": roof,
             "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "converged_walks_per_s": conv / wall,
             "adjoint_converged_chains_per_s": conv / (adj_ms / 1e3),
             "theta_grad_norm": float(gth.norm())}
@@ -393,16 +524,19 @@ def main():
         if m.any():
             per_k[str(k)] = {"chains": int(m.sum()), "converged": int((conv & m).sum()),
                              "converged_walks_per_s": float((conv & m).sum() / (headline_ms / 1e3))}
+    per_length = per_length_leg(M, W, args, params, scene, ep) if (args.per_length and name == "slab_uneven") else None
     if args.adjoint_n > 0:
         forms["+adjoint"] = adjoint_leg(M, W, args, tuned_all=load_tuned(args.tuned, "slab_adjoint"), cone=cone)
     if args.guide_n > 0:
         forms["guided+trials"] = guide_leg(M, W, args)
+    configs = configs_leg(M, W, args) if args.configs_leg else None
 
     # untimed counting pass: algorithmic work of one walk launch
     prm_c = params("plain")
     p, q, st = M.sample_seeds(scene, dep, prm_c)
     _, _, outs_c, counts = M.walk_count(scene, prm_c, dep, p, q, st)
     flops = sum(FLOPS_PER_UNIT[k] * counts[k] for k in FLOPS_PER_UNIT)
+    flops_survey = sum(SURVEY_FLOPS_PER_UNIT[k] * counts[k] for k in SURVEY_FLOPS_PER_UNIT)
     walk_s = R["walk_ms"] / 1e3
     achieved = flops / walk_s / 1e12
     # algorithmic HBM bytes of the walk launch: endpoints (38 B), seed chain in
@@ -420,6 +554,10 @@ def main():
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "kernel": "walk (persistent)" if main_form == "persistent" else "walk (plain)",
                 "flops_per_launch": flops, "counts_per_launch": counts,
+                "walk_launch_ms": R["walk_ms"],
+                "at_scope_prices": {"flops_per_launch": flops_survey,
+                                    "achieved": flops_survey / walk_s / 1e12,
+                                    "frac": flops_survey / walk_s / 1e12 / PEAK_FP32_TFLOPS},
                 "hbm_algorithmic_GBs": hbm_bytes / walk_s / 1e9}
 
     out = {
@@ -438,6 +576,8 @@ def main():
         "config": {"workload": name, "chains": N, "scene_tris": int(sc.n_tris), "max_len": MAX_LEN[name],
                    "form": headline_form, "converged_fraction": n_conv / N, "tuned": tuned},
         "per_k": per_k,
+        "per_length_isolated": per_length,
+        "configs": configs,
         # outcome of every chain of the main form's last step, and the Newton
         # trials the walks used (index = trials)
         "status_hist": {(M.STATUS_NAMES + ["needs_fp64"])[k]: int(v)

@@ -70,6 +70,7 @@ def _declare(L):
                            P, P, P, P, C.c_int]
     L.orc_inv_prob.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, C.c_int,
                                C.c_int, U64, D, P, P, P, C.c_int]
+    L.orc_validate.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, C.c_int]
     L.orc_scene_set_theta.restype = C.c_int
     L.orc_scene_set_theta.argtypes = [P, C.c_int, P]
     L.orc_adjoint.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
@@ -242,6 +243,22 @@ def walk(osc: Scene, ep, seed_prim, seed_pos, seed_status=None, polish=True, prm
     return out
 
 
+def validate(osc: Scene, ep, prim, pos, prm=None, nthreads=0):
+    """FP64 admissibility of given chains (e.g. the GPU's converged chains):
+    polish from the given vertices, then side and visibility tests.  Returns
+    a dict of per-chain arrays: ok, residual, moved, side, visible,
+    same_prims."""
+    N = ep.n
+    prm = prm or params(osc.scale)
+    out = dict(ok=np.zeros(N, np.int8), residual=np.zeros(N), moved=np.zeros(N), side=np.zeros(N, np.int8),
+               visible=np.zeros(N, np.int8), same_prims=np.zeros(N, np.int8))
+    lib().orc_validate(osc.h, C.byref(prm), N, _p(_c(ep.xD, np.float64)), _p(_c(ep.xL, np.float64)),
+                       _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)), _p(_c(prim, np.int32)),
+                       _p(_c(pos, np.float64)), _p(out["ok"]), _p(out["residual"]), _p(out["moved"]),
+                       _p(out["side"]), _p(out["visible"]), _p(out["same_prims"]), nthreads)
+    return out
+
+
 def inv_prob(osc: Scene, ep, tgt_prim, tgt_pos, tgt_status, max_trials=64, repeats=1, seed=0, alpha=0.5,
              guide=None, prm=None, nthreads=0):
     N = ep.n
@@ -297,3 +314,156 @@ def adjoint(osc: Scene, ep, prim, pos, status, grad_pos, grad_G, theta=None, prm
                       _p(_c(prim, np.int32)), _p(_c(pos, np.float64)), _p(_c(status, np.int8)), _p(gp), _p(gg),
                       _p(th), _p(gxD), _p(gxL), _p(gth), _p(ok), nthreads)
     return gxD, gxL, gth[:, :P], ok
+
+
+# ---------------------------------------------------------------------------
+# the paper's guide: 6-D tree over (x_D, x_L), per-leaf length / type
+# histograms and vMF lobes (Sec. 5.5, 5.6)
+# ---------------------------------------------------------------------------
+
+def _declare_stree(L):
+    L.orc_stree_build.restype = P
+    L.orc_stree_build.argtypes = [C.c_int, P, P, P, D, D, C.c_int, D, D]
+    L.orc_stree_destroy.argtypes = [P]
+    L.orc_stree_set_prior.argtypes = [P, P, D, D]
+    L.orc_stree_n_nodes.restype = C.c_int
+    L.orc_stree_n_nodes.argtypes = [P]
+    L.orc_stree_n_lobes.restype = C.c_int
+    L.orc_stree_n_lobes.argtypes = [P]
+    L.orc_stree_nodes.argtypes = [P] + [P] * 12
+    L.orc_stree_node_entries.restype = C.c_int
+    L.orc_stree_node_entries.argtypes = [P, C.c_int, P, P]
+    L.orc_stree_lobes.argtypes = [P, P, P, P, P, P]
+    L.orc_stree_lookup.argtypes = [P, C.c_int, P, P, P]
+    L.orc_vmf_pdf.restype = D
+    L.orc_vmf_pdf.argtypes = [P, D, P]
+    L.orc_vmf_sample.argtypes = [P, D, C.c_int, P, P]
+    L.orc_stree_sample_seeds.argtypes = [P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, U64, U64, P, P, P, P,
+                                         P, P, C.c_int]
+    L.orc_stree_inv_prob.argtypes = [P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, C.c_int,
+                                     C.c_int, U64, P, P, P, P, C.c_int]
+
+
+def sample_records(xD, xL, wD, w, n, types):
+    """Pack sub-path samples into [N, 16] float32 records:
+    x_D (3), x_L (3), w_D (3), w, n, tau, 0 x 4."""
+    N = len(w)
+    r = np.zeros((N, 16), np.float32)
+    r[:, 0:3] = xD
+    r[:, 3:6] = xL
+    r[:, 6:9] = wD
+    r[:, 9] = w
+    r[:, 10] = n
+    r[:, 11] = types
+    return r
+
+
+class STree:
+    """The paper's guide built from sample records (see sample_records)."""
+
+    def __init__(self, records, lo, hi, eps=0.1, thr_scale=1.0, max_depth=20, sigma_min=1e-3, sigma_lone=0.1,
+                 p0n=None, alpha=0.5, p_transmit=0.5):
+        L = lib()
+        if not hasattr(L, "_stree_declared"):
+            _declare_stree(L)
+            L._stree_declared = True
+        self.rec = _c(records, np.float32).reshape(-1, 16)
+        self.lo = _c(lo, np.float64)
+        self.hi = _c(hi, np.float64)
+        self.h = L.orc_stree_build(len(self.rec), _p(self.rec), _p(self.lo), _p(self.hi), float(eps),
+                                   float(thr_scale), int(max_depth), float(sigma_min), float(sigma_lone))
+        self.set_prior(np.full(8, 1.0 / 8) if p0n is None else p0n, alpha, p_transmit)
+
+    def set_prior(self, p0n, alpha=0.5, p_transmit=0.5):
+        self.p0n = _c(p0n, np.float64)
+        self.alpha, self.p_transmit = float(alpha), float(p_transmit)
+        lib().orc_stree_set_prior(self.h, _p(self.p0n), self.alpha, self.p_transmit)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_stree_destroy(self.h)
+            self.h = None
+
+    def nodes(self):
+        n = lib().orc_stree_n_nodes(self.h)
+        d = dict(axis=np.zeros(n, np.int32), mid=np.zeros(n), child=np.zeros(n, np.int32),
+                 depth=np.zeros(n, np.int32), lo=np.zeros((n, 6)), hi=np.zeros((n, 6)),
+                 n_entries=np.zeros(n, np.int32), n_own=np.zeros(n, np.int32), W=np.zeros(n),
+                 Wn=np.zeros((n, 8)), n_groups=np.zeros(n, np.int32), lobe0=np.zeros(n, np.int32))
+        lib().orc_stree_nodes(self.h, *[_p(d[k]) for k in ("axis", "mid", "child", "depth", "lo", "hi", "n_entries",
+                                                           "n_own", "W", "Wn", "n_groups", "lobe0")])
+        return d
+
+    def node_entries(self, k, count):
+        ids = np.zeros(max(1, count), np.int32)
+        own = np.zeros(max(1, count), np.int8)
+        m = lib().orc_stree_node_entries(self.h, int(k), _p(ids), _p(own))
+        return ids[:m], own[:m]
+
+    def lobes(self):
+        m = lib().orc_stree_n_lobes(self.h)
+        d = dict(mu=np.zeros((m, 3)), kappa=np.zeros(m), w=np.zeros(m), n=np.zeros(m, np.int32),
+                 type=np.zeros(m, np.int32))
+        lib().orc_stree_lobes(self.h, *[_p(d[k]) for k in ("mu", "kappa", "w", "n", "type")])
+        return d
+
+    def lookup(self, xD, xL):
+        xD = _c(xD, np.float64)
+        xL = _c(xL, np.float64)
+        N = xD.shape[1]
+        out = np.zeros(N, np.int32)
+        lib().orc_stree_lookup(self.h, N, _p(xD), _p(xL), _p(out))
+        return out
+
+
+def vmf_pdf(mu, kappa, w):
+    L = lib()
+    if not hasattr(L, "_stree_declared"):
+        _declare_stree(L)
+        L._stree_declared = True
+    return L.orc_vmf_pdf(_p(_c(mu, np.float64)), float(kappa), _p(_c(w, np.float64)))
+
+
+def vmf_sample(mu, kappa, u):
+    L = lib()
+    if not hasattr(L, "_stree_declared"):
+        _declare_stree(L)
+        L._stree_declared = True
+    u = _c(u, np.float64).reshape(-1, 2)
+    out = np.zeros((len(u), 3))
+    L.orc_vmf_sample(_p(_c(mu, np.float64)), float(kappa), len(u), _p(u), _p(out))
+    return out
+
+
+def stree_sample_seeds(osc: Scene, st: STree, ep, seed=0, trial=0, n_fixed=None, prm=None, nthreads=0):
+    """Seeds from the paper's guide; returns (n, type, P(n), prim, pos, status)."""
+    N = ep.n
+    prm = prm or params(osc.scale)
+    n_out = np.zeros(N, np.uint8)
+    t_out = np.zeros(N, np.uint8)
+    pn = np.zeros(N)
+    prim = np.zeros((KMAX, N), np.int32)
+    pos = np.zeros((3, KMAX, N))
+    status = np.zeros(N, np.int8)
+    nf = None if n_fixed is None else _c(n_fixed, np.uint8)
+    lib().orc_stree_sample_seeds(osc.h, st.h, C.byref(prm), N, _p(_c(ep.xD, np.float64)), _p(_c(ep.nD, np.float64)),
+                                 _p(_c(ep.xL, np.float64)), _p(nf), _p(_c(ep.obj1, np.int32)), int(seed), int(trial),
+                                 _p(n_out), _p(t_out), _p(pn), _p(prim), _p(pos), _p(status), nthreads)
+    return n_out, t_out, pn, prim, pos, status
+
+
+def stree_inv_prob(osc: Scene, st: STree, ep, length, types, tgt_prim, tgt_pos, tgt_status, max_trials=64,
+                   repeats=1, seed=0, prm=None, nthreads=0):
+    """Reciprocal probability with the paper's guide; returns (trials, inv_prob = K / P(n), truncated, P(n))."""
+    N = ep.n
+    prm = prm or params(osc.scale)
+    trials = np.zeros(N, np.int32)
+    ip = np.zeros(N)
+    tr = np.zeros(N, np.int8)
+    pn = np.zeros(N)
+    lib().orc_stree_inv_prob(osc.h, st.h, C.byref(prm), N, _p(_c(ep.xD, np.float64)), _p(_c(ep.nD, np.float64)),
+                             _p(_c(ep.xL, np.float64)), _p(_c(length, np.uint8)), _p(_c(types, np.uint8)),
+                             _p(_c(ep.obj1, np.int32)), _p(_c(tgt_prim, np.int32)), _p(_c(tgt_pos, np.float64)),
+                             _p(_c(tgt_status, np.int8)), int(max_trials), int(repeats), int(seed), _p(trials), _p(ip),
+                             _p(tr), _p(pn), nthreads)
+    return trials, ip, tr, pn

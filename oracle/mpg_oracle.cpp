@@ -895,6 +895,9 @@ static bool sample_guided_point(const Scene& s, const Guide& g, int cell, uint64
   return false;
 }
 
+static int8_t deduce_chain(const Scene& s, const Params& p, int n, int type, const double* coins, double p_transmit,
+                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out);
+
 static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n, int type, int obj1,
                           const V3d& xD, const V3d& nD, uint64_t seed, uint64_t chain, uint64_t trial, double alpha,
                           int* prim, V3d* pos) {
@@ -911,6 +914,18 @@ static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n
     ok = sample_p0_point(s, p, obj1, xD, nD, U.u[1], U.u[2], U.u[3], &pt);
   }
   if (!ok) return ST_SEED_INVALID;
+  return deduce_chain(s, p, n, type, nullptr, 0.0, xD, pt, prim, pos, nullptr);
+}
+
+// Eq. (deduction): x_1 = r(x_D, w_D) with w_D towards pt, then x_i = r(x_{i-1},
+// s_tau(x_{i-1}, ...)) with the scattering type of vertex i-1.  With coins
+// == nullptr the type is the given one; otherwise the type of each vertex is
+// decided when the ray reaches it, as a path tracer would (Sec. 5.4): a
+// mirror reflects, a dielectric transmits when its coin is below
+// p_transmit and reflects otherwise; the decided type is returned in
+// *type_out.  Returns 0 or ST_SEED_INVALID.
+static int8_t deduce_chain(const Scene& s, const Params& p, int n, int type, const double* coins, double p_transmit,
+                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out) {
   const double tmin = p.tmin_rel * p.scale;
   V3d o = xD, d = pt - xD;
   double len = norm(d);
@@ -942,9 +957,14 @@ static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n
     if (!h.ok) return ST_SEED_INVALID;
     prim[i] = h.prim;
     pos[i] = o + d * h.t;
+    if (coins) {
+      bool transmit = s.mat[s.prim_obj(prim[i])] == MAT_DIELECTRIC && coins[i] < p_transmit;
+      type = transmit ? (type | (1 << i)) : (type & ~(1 << i));
+    }
   }
   for (int i = 0; i < n; ++i)
     if (((type >> i) & 1) && s.mat[s.prim_obj(prim[i])] != MAT_DIELECTRIC) return ST_SEED_INVALID;
+  if (type_out) *type_out = type;
   return ST_CONVERGED;  // 0: valid seed
 }
 
@@ -1307,6 +1327,250 @@ static bool chain_gradient(const Scene& s, const Params& p, int n, int type, con
   return true;
 }
 
+
+// ---------------------------------------------------------------------------
+// The paper's guide (Sec. 5.5, Sec. 5.6): sub-path samples (x_D, x_L, n, tau,
+// w_D, w) organised in a binary tree over the 6-D configuration (x_D, x_L);
+// per leaf, discrete distributions of the length and of the type (Eq. eq_div2)
+// and a von Mises-Fisher mixture over w_D with one lobe per sample.
+//
+// Tree (Sec. 5.6): a node whose sample count exceeds c sqrt(|S|) is split at
+// the middle of its longest side (lowest axis on ties).  Child overlap: a
+// node holds every sample of its parent that lies inside the node's box
+// dilated by eps times the node's own extent along the split axis (the
+// paper copies about eps k samples across the split plane each way and drops
+// samples far from a node's box; a dilation by eps of the node's size does
+// both for locally even sample density).  A sample is "own" in the one leaf
+// whose undilated box holds it.  Nodes are numbered breadth first, children
+// left (below the middle) then right.
+//
+// Leaf (Sec. 5.5): P_e(n) = W_n / W and P_e(tau | n) = W_{n,tau} / W_n from
+// the weights w of the leaf's samples; lobe j of group (n, tau) has mean
+// direction mu_j = w_D of sample j, concentration kappa_j = sigma_j^-2, where
+// sigma_j is the angle to the nearest other direction of the same group
+// (floored at sigma_min; sigma_lone for a sample alone in its group), and
+// weight proportional to w_j.  Groups are ordered by (n, tau), lobes by
+// sample index.
+// ---------------------------------------------------------------------------
+struct SSample {
+  double p[6];  // x_D, x_L
+  V3d dir;      // w_D (unit)
+  double w;
+  int n, type;
+};
+
+struct STNode {
+  double lo[6], hi[6];
+  int depth = 0, axis = -1;
+  double mid = 0.0;
+  int child = -1;  // left child; right = child + 1
+  std::vector<int> entries;
+  std::vector<char> own;
+};
+
+struct STGroup {
+  int n, type;
+  double weight;
+  int first, count;  // lobes [first, first + count) of the leaf
+};
+
+struct STLeaf {
+  double W = 0.0, Wn[KMAX + 1] = {0};
+  int own = 0;
+  std::vector<STGroup> groups;
+  std::vector<V3d> mu;
+  std::vector<double> kappa, w;
+};
+
+struct STree {
+  std::vector<STNode> nodes;
+  std::vector<STLeaf> leaf;  // by node id (empty for inner nodes)
+  double p0n[KMAX + 1] = {0};  // P_0(n), n = 1..8
+  double alpha = 0.5;
+  double p_transmit = 0.5;
+  double sigma_min = 1e-3, sigma_lone = 0.1;
+};
+
+static double chord_angle(const V3d& a, const V3d& b) {
+  double c = norm(a - b);
+  return 2.0 * std::asin(std::min(1.0, 0.5 * c));
+}
+
+static void stree_build(const std::vector<SSample>& S, const double lo[6], const double hi[6], double eps,
+                        double thr_scale, int max_depth, STree* t) {
+  t->nodes.clear();
+  t->leaf.clear();
+  STNode root;
+  for (int a = 0; a < 6; ++a) { root.lo[a] = lo[a]; root.hi[a] = hi[a]; }
+  int n_valid = 0;
+  for (int j = 0; j < (int)S.size(); ++j) {
+    const SSample& q = S[j];
+    if (!(q.w > 0.0) || q.n < 1 || q.n > KMAX) continue;
+    bool in = true;
+    for (int a = 0; a < 6; ++a) in = in && q.p[a] >= lo[a] && q.p[a] <= hi[a];
+    if (!in) continue;
+    root.entries.push_back(j);
+    root.own.push_back(1);
+    ++n_valid;
+  }
+  const double thr = thr_scale * std::sqrt((double)n_valid);
+  t->nodes.push_back(root);
+  for (size_t k = 0; k < t->nodes.size(); ++k) {
+    if (!((double)t->nodes[k].entries.size() > thr) || t->nodes[k].depth >= max_depth) continue;
+    STNode nd = t->nodes[k];
+    int ax = 0;
+    for (int a = 1; a < 6; ++a)
+      if (nd.hi[a] - nd.lo[a] > nd.hi[ax] - nd.lo[ax]) ax = a;
+    double mid = 0.5 * (nd.lo[ax] + nd.hi[ax]);
+    double dil = eps * (mid - nd.lo[ax]);  // eps times the child's extent along the split axis
+    STNode L, R;
+    for (int a = 0; a < 6; ++a) { L.lo[a] = R.lo[a] = nd.lo[a]; L.hi[a] = R.hi[a] = nd.hi[a]; }
+    L.hi[ax] = mid;
+    R.lo[ax] = mid;
+    L.depth = R.depth = nd.depth + 1;
+    for (size_t e = 0; e < nd.entries.size(); ++e) {
+      double v = S[nd.entries[e]].p[ax];
+      if (v >= nd.lo[ax] - dil && v < mid + dil) {
+        L.entries.push_back(nd.entries[e]);
+        L.own.push_back(nd.own[e] && v < mid);
+      }
+      if (v >= mid - dil && v < nd.hi[ax] + dil) {
+        R.entries.push_back(nd.entries[e]);
+        R.own.push_back(nd.own[e] && v >= mid);
+      }
+    }
+    t->nodes[k].axis = ax;
+    t->nodes[k].mid = mid;
+    t->nodes[k].child = (int)t->nodes.size();
+    t->nodes.push_back(L);
+    t->nodes.push_back(R);
+  }
+  t->leaf.assign(t->nodes.size(), STLeaf());
+  for (size_t k = 0; k < t->nodes.size(); ++k) {
+    const STNode& nd = t->nodes[k];
+    if (nd.axis >= 0) continue;
+    STLeaf& lf = t->leaf[k];
+    std::vector<std::pair<std::pair<int, int>, int>> order;  // ((n, type), sample)
+    for (size_t e = 0; e < nd.entries.size(); ++e) {
+      const SSample& q = S[nd.entries[e]];
+      lf.W += q.w;
+      lf.Wn[q.n] += q.w;
+      lf.own += nd.own[e] ? 1 : 0;
+      order.push_back({{q.n, q.type}, nd.entries[e]});
+    }
+    std::sort(order.begin(), order.end());
+    for (size_t i = 0; i < order.size();) {
+      size_t e = i;
+      while (e < order.size() && order[e].first == order[i].first) ++e;
+      STGroup gr;
+      gr.n = order[i].first.first;
+      gr.type = order[i].first.second;
+      gr.weight = 0.0;
+      gr.first = (int)lf.mu.size();
+      gr.count = (int)(e - i);
+      for (size_t a = i; a < e; ++a) {
+        const SSample& q = S[order[a].second];
+        double sig = kInf;
+        for (size_t b = i; b < e; ++b)
+          if (b != a) sig = std::min(sig, chord_angle(q.dir, S[order[b].second].dir));
+        sig = gr.count == 1 ? t->sigma_lone : std::max(sig, t->sigma_min);
+        lf.mu.push_back(q.dir);
+        lf.kappa.push_back(1.0 / (sig * sig));
+        lf.w.push_back(q.w);
+        gr.weight += q.w;
+      }
+      lf.groups.push_back(gr);
+      i = e;
+    }
+  }
+}
+
+// Leaf of a configuration: descend by the split planes (undilated).
+static int stree_leaf(const STree& t, const double p[6]) {
+  int k = 0;
+  while (t.nodes[k].axis >= 0) k = t.nodes[k].child + (p[t.nodes[k].axis] < t.nodes[k].mid ? 0 : 1);
+  return k;
+}
+
+// Inverse CDF of a discrete distribution given by non-negative weights.
+static int pick(const double* wts, int count, double total, double u) {
+  double target = u * total, acc = 0.0;
+  for (int i = 0; i < count; ++i) {
+    acc += wts[i];
+    if (target < acc) return i;
+  }
+  for (int i = count - 1; i >= 0; --i)
+    if (wts[i] > 0.0) return i;
+  return count - 1;
+}
+
+// vMF lobe (Eq. vMF) sampling by inversion of the cosine's distribution:
+// cos theta = 1 + log(u + (1 - u) exp(-2 kappa)) / kappa, phi uniform.
+static V3d sample_vmf(const V3d& mu, double kappa, double u1, double u2) {
+  double ct = 1.0 + std::log(u1 + (1.0 - u1) * std::exp(-2.0 * kappa)) / kappa;
+  ct = std::max(-1.0, std::min(1.0, ct));
+  double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  V3d b1, b2;
+  onb(mu, &b1, &b2);
+  double ph = 2.0 * kPi * u2;
+  return b1 * (st * std::cos(ph)) + b2 * (st * std::sin(ph)) + mu * ct;
+}
+
+static double vmf_pdf(const V3d& mu, double kappa, const V3d& w) {
+  // kappa / (4 pi sinh kappa) exp(kappa mu.w), written with exp(kappa (mu.w - 1)) for large kappa
+  return kappa / (2.0 * kPi * (1.0 - std::exp(-2.0 * kappa))) * std::exp(kappa * (dot(mu, w) - 1.0));
+}
+
+// P(n | x_D, x_L) of the defensive one-sample mixture (Sec. 5.5).
+static double stree_pn(const STree& t, const STLeaf& lf, int n) {
+  if (!(lf.W > 0.0)) return t.p0n[n];
+  return t.alpha * t.p0n[n] + (1.0 - t.alpha) * lf.Wn[n] / lf.W;
+}
+
+// One seed from the paper's guide: the length n (unless given, n_fixed > 0)
+// from alpha P_0(n) + (1 - alpha) P_e(n), then (w_D, tau) from
+// alpha p_0 + (1 - alpha) p_e (Sec. 5.5, defensive sampling); p_0 takes x_1
+// by the obj1 mode and decides tau by ray tracing, p_e picks tau from
+// P_e(tau | n), a lobe by weight and w_D from the lobe.  Random numbers: block
+// (chain, trial, 0) for the choices, block 1 for p_0's point, block 2 for the
+// vertex coins.  Returns the status and n, tau, P(n).
+static int8_t stree_sample(const Scene& s, const STree& t, const Params& p, int n_fixed, int obj1, const V3d& xD,
+                           const V3d& nD, const V3d& xL, uint64_t seed, uint64_t chain, uint64_t trial, int* n_out,
+                           int* type_out, double* pn_out, int* prim, V3d* pos) {
+  if (!finite3(xD) || !finite3(xL)) return ST_BAD_INPUT;
+  double q[6] = {xD.x, xD.y, xD.z, xL.x, xL.y, xL.z};
+  const STLeaf& lf = t.leaf[stree_leaf(t, q)];
+  Uniforms U = draw(seed, chain, trial, 0);
+  int n = n_fixed;
+  if (n < 1) {
+    double pe[KMAX];
+    for (int k = 1; k <= KMAX; ++k) pe[k - 1] = lf.W > 0.0 ? lf.Wn[k] : 0.0;
+    bool prior = !(lf.W > 0.0) || U.u[0] < t.alpha;
+    n = 1 + (prior ? pick(t.p0n + 1, KMAX, 1.0, U.u[1]) : pick(pe, KMAX, lf.W, U.u[1]));
+  }
+  if (n < 1 || n > KMAX) return ST_BAD_INPUT;
+  *n_out = n;
+  *pn_out = stree_pn(t, lf, n);
+  // groups of this length
+  std::vector<double> gw;
+  std::vector<int> gi;
+  double Wn = 0.0;
+  for (size_t g = 0; g < lf.groups.size(); ++g)
+    if (lf.groups[g].n == n) { gw.push_back(lf.groups[g].weight); gi.push_back((int)g); Wn += lf.groups[g].weight; }
+  bool prior = !(Wn > 0.0) || U.u[2] < t.alpha;
+  if (prior) {
+    Uniforms V = draw(seed, chain, trial, 1), Cn = draw(seed, chain, trial, 2);
+    V3d pt;
+    if (!sample_p0_point(s, p, obj1, xD, nD, V.u[1], V.u[2], V.u[3], &pt)) return ST_SEED_INVALID;
+    return deduce_chain(s, p, n, 0, Cn.u, t.p_transmit, xD, pt, prim, pos, type_out);
+  }
+  const STGroup& gr = lf.groups[gi[pick(gw.data(), (int)gw.size(), Wn, U.u[3])]];
+  int j = gr.first + pick(&lf.w[gr.first], gr.count, gr.weight, U.u[4]);
+  V3d w = sample_vmf(lf.mu[j], lf.kappa[j], U.u[5], U.u[6]);
+  *type_out = gr.type;
+  return deduce_chain(s, p, n, gr.type, nullptr, 0.0, xD, xD + w, prim, pos, nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // threads
 // ---------------------------------------------------------------------------
@@ -1570,6 +1834,59 @@ void orc_walk(void* sp, const orc_params* pp, int N, const double* xD, const dou
   });
 }
 
+// Admissibility of externally computed chains (e.g. FP32 results): each
+// given vertex is first put exactly onto its primitive (radial projection on
+// a sphere, orthogonal projection on a triangle's plane: rounded coordinates
+// lie slightly off the surface, and the walk's steps assume a point on it),
+// then the oracle's FP64 Newton polish runs within the scene, then the side
+// conditions and the shadow ray of the polished chain are tested.  Per
+// chain: ok (the chain could be loaded), the residual max-norm after the
+// polish, the largest vertex displacement of the polish, side, visible, and
+// whether the polish kept every primitive id.
+void orc_validate(void* sp, const orc_params* pp, int N, const double* xD, const double* xL, const uint8_t* len,
+                  const uint8_t* type, const int32_t* prim_in, const double* pos_in, int8_t* ok, double* resid,
+                  double* moved, int8_t* side, int8_t* visible, int8_t* same_prims, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    int n = len[c];
+    ok[c] = 0; resid[c] = kInf; moved[c] = kInf; side[c] = 0; visible[c] = 0; same_prims[c] = 0;
+    if (n < 1 || n > KMAX) return;
+    int prim[KMAX];
+    V3d pos[KMAX];
+    for (int i = 0; i < n; ++i) {
+      prim[i] = prim_in[(size_t)i * N + c];
+      pos[i] = V3d(pos_in[((size_t)0 * KMAX + i) * N + c], pos_in[((size_t)1 * KMAX + i) * N + c],
+                   pos_in[((size_t)2 * KMAX + i) * N + c]);
+      if (prim[i] >= s.ntri() || (prim[i] < 0 && -1 - prim[i] >= (int)s.sr.size())) return;
+      if (prim[i] < 0) {
+        int k = -1 - prim[i];
+        pos[i] = s.sc[k] + normalize(pos[i] - s.sc[k]) * s.sr[k];
+      } else {
+        V3d a, b, cc;
+        tri_verts(s, prim[i], &a, &b, &cc);
+        V3d ng = normalize(cross(b - a, cc - a));
+        pos[i] = pos[i] - ng * dot(pos[i] - a, ng);
+      }
+    }
+    WalkResult r;
+    if (!load_chain(s, n, type[c], get3d(xD, N, c), get3d(xL, N, c), prim, pos, &r.chain)) return;
+    ok[c] = 1;
+    polish(s, p, &r);
+    resid[c] = r.residual;
+    double mv = 0.0;
+    bool same = true;
+    for (int i = 0; i < n; ++i) {
+      mv = std::max(mv, norm(r.chain.v[i].x - pos[i]));
+      same = same && r.chain.v[i].prim == prim[i];
+    }
+    moved[c] = mv;
+    same_prims[c] = same ? 1 : 0;
+    side[c] = side_ok(r.chain) ? 1 : 0;
+    visible[c] = visible_to_light(s, p, r.chain) ? 1 : 0;
+  });
+}
+
 // Reciprocal probability by repeated independent trials (Sec. 5.8): for a
 // converged target, draw seeds from the same distribution with fresh random
 // numbers (trial counter 1 + r M + k - 1) and walk until the same chain is
@@ -1706,6 +2023,203 @@ void orc_adjoint(void* sp, const orc_params* pp, int N, const double* xD, const 
     ok[c] = 1;
     for (int a = 0; a < 3; ++a) { grad_xD[(size_t)a * N + c] = gxD[a]; grad_xL[(size_t)a * N + c] = gxL[a]; }
     for (int k = 0; k < P; ++k) grad_theta[(size_t)c * P + k] = gth[k];
+  });
+}
+
+
+// ---------------------------------------------------------------------------
+// The paper's guide: tree, leaf distributions, sampling and trials.
+// Sample records: float [N][16] = x_D (3), x_L (3), w_D (3), w, n, tau, 0 x 4.
+// ---------------------------------------------------------------------------
+void* orc_stree_build(int N, const float* rec, const double* lo, const double* hi, double eps, double thr_scale,
+                      int max_depth, double sigma_min, double sigma_lone) {
+  std::vector<SSample> S(N);
+  for (int j = 0; j < N; ++j) {
+    const float* r = rec + 16 * (size_t)j;
+    for (int a = 0; a < 6; ++a) S[j].p[a] = r[a];
+    S[j].dir = normalize(V3d(r[6], r[7], r[8]));
+    S[j].w = std::isfinite(r[9]) ? r[9] : 0.0;
+    S[j].n = (int)r[10];
+    S[j].type = (int)r[11];
+    for (int a = 0; a < 6; ++a)
+      if (!std::isfinite(r[a])) S[j].w = 0.0;
+  }
+  STree* t = new STree();
+  t->sigma_min = sigma_min;
+  t->sigma_lone = sigma_lone;
+  stree_build(S, lo, hi, eps, thr_scale, max_depth, t);
+  return t;
+}
+
+void orc_stree_destroy(void* h) { delete (STree*)h; }
+
+void orc_stree_set_prior(void* h, const double* p0n, double alpha, double p_transmit) {
+  STree* t = (STree*)h;
+  double tot = 0.0;
+  for (int k = 0; k < KMAX; ++k) tot += p0n[k];
+  for (int k = 1; k <= KMAX; ++k) t->p0n[k] = tot > 0.0 ? p0n[k - 1] / tot : 0.0;
+  t->alpha = alpha;
+  t->p_transmit = p_transmit;
+}
+
+int orc_stree_n_nodes(void* h) { return (int)((STree*)h)->nodes.size(); }
+int orc_stree_n_lobes(void* h) {
+  int n = 0;
+  for (const STLeaf& l : ((STree*)h)->leaf) n += (int)l.mu.size();
+  return n;
+}
+
+// per node: axis (-1 leaf), mid, child, depth, box lo/hi [6], entries, own,
+// leaf weight W and W_n [8], number of groups, first lobe (leaf-major order)
+void orc_stree_nodes(void* h, int32_t* axis, double* mid, int32_t* child, int32_t* depth, double* lo, double* hi,
+                     int32_t* n_entries, int32_t* n_own, double* W, double* Wn, int32_t* n_groups, int32_t* lobe0) {
+  const STree& t = *(STree*)h;
+  int lobes = 0;
+  for (size_t k = 0; k < t.nodes.size(); ++k) {
+    const STNode& nd = t.nodes[k];
+    axis[k] = nd.axis; mid[k] = nd.mid; child[k] = nd.child; depth[k] = nd.depth;
+    for (int a = 0; a < 6; ++a) { lo[6 * k + a] = nd.lo[a]; hi[6 * k + a] = nd.hi[a]; }
+    n_entries[k] = (int)nd.entries.size();
+    int own = 0;
+    for (char o : nd.own) own += o;
+    n_own[k] = own;
+    const STLeaf& lf = t.leaf[k];
+    W[k] = lf.W;
+    for (int q = 0; q < KMAX; ++q) Wn[KMAX * k + q] = lf.Wn[q + 1];
+    n_groups[k] = (int)lf.groups.size();
+    lobe0[k] = lobes;
+    lobes += (int)lf.mu.size();
+  }
+}
+
+// the entries (sample ids) and own flags of one node
+int orc_stree_node_entries(void* h, int k, int32_t* ids, int8_t* own) {
+  const STNode& nd = ((STree*)h)->nodes[k];
+  for (size_t e = 0; e < nd.entries.size(); ++e) { ids[e] = nd.entries[e]; own[e] = nd.own[e]; }
+  return (int)nd.entries.size();
+}
+
+// lobes in leaf-major, group, sample order: mean direction, kappa, weight,
+// and the group's (n, type)
+void orc_stree_lobes(void* h, double* mu, double* kappa, double* w, int32_t* n, int32_t* type) {
+  const STree& t = *(STree*)h;
+  size_t q = 0;
+  for (const STLeaf& lf : t.leaf)
+    for (const STGroup& g : lf.groups)
+      for (int j = g.first; j < g.first + g.count; ++j, ++q) {
+        mu[3 * q] = lf.mu[j].x; mu[3 * q + 1] = lf.mu[j].y; mu[3 * q + 2] = lf.mu[j].z;
+        kappa[q] = lf.kappa[j]; w[q] = lf.w[j]; n[q] = g.n; type[q] = g.type;
+      }
+}
+
+void orc_stree_lookup(void* h, int N, const double* xD, const double* xL, int32_t* leaf) {
+  const STree& t = *(STree*)h;
+  for (int c = 0; c < N; ++c) {
+    double q[6] = {xD[c], xD[N + c], xD[2 * N + c], xL[c], xL[N + c], xL[2 * N + c]};
+    leaf[c] = stree_leaf(t, q);
+  }
+}
+
+double orc_vmf_pdf(const double* mu, double kappa, const double* w) {
+  return vmf_pdf(V3d(mu[0], mu[1], mu[2]), kappa, V3d(w[0], w[1], w[2]));
+}
+void orc_vmf_sample(const double* mu, double kappa, int N, const double* u, double* out) {
+  V3d m(mu[0], mu[1], mu[2]);
+  for (int i = 0; i < N; ++i) {
+    V3d w = sample_vmf(m, kappa, u[2 * i], u[2 * i + 1]);
+    out[3 * i] = w.x; out[3 * i + 1] = w.y; out[3 * i + 2] = w.z;
+  }
+}
+
+// Seeds from the paper's guide: n_fixed[c] > 0 keeps that length, 0 samples
+// it.  Outputs n, type, P(n), the seed chain and the status.
+void orc_stree_sample_seeds(void* sp, void* h, const orc_params* pp, int N, const double* xD, const double* nD,
+                            const double* xL, const uint8_t* n_fixed, const int32_t* obj1, uint64_t seed,
+                            uint64_t trial, uint8_t* n_out, uint8_t* type_out, double* pn_out, int32_t* prim_out,
+                            double* pos_out, int8_t* status, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  const STree& t = *(STree*)h;
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    int prim[KMAX], n = 0, type = 0;
+    V3d pos[KMAX];
+    double pn = 0.0;
+    for (int i = 0; i < KMAX; ++i) { prim[i] = INT32_MIN; pos[i] = V3d(); }
+    int8_t st = stree_sample(s, t, p, n_fixed ? n_fixed[c] : 0, obj1[c], get3d(xD, N, c), get3d(nD, N, c),
+                             get3d(xL, N, c), seed, (uint64_t)c, trial, &n, &type, &pn, prim, pos);
+    status[c] = st;
+    n_out[c] = (uint8_t)n;
+    type_out[c] = (uint8_t)type;
+    pn_out[c] = pn;
+    for (int i = 0; i < KMAX; ++i) {
+      bool have = st == 0 && i < n;
+      prim_out[(size_t)i * N + c] = have ? prim[i] : INT32_MIN;
+      for (int a = 0; a < 3; ++a) pos_out[((size_t)a * KMAX + i) * N + c] = have ? pos[i][a] : 0.0;
+    }
+  });
+}
+
+// Reciprocal probability with the paper's guide (Sec. 5.8): n is the
+// target's and is kept across trials; each trial draws (w_D, tau) from the
+// same mixture (trial counters 1 + r M + k - 1), walks, and matches the
+// target (same tau, objects, vertices within match_rel L).  inv_prob =
+// mean_r K_r / P(n).
+void orc_stree_inv_prob(void* sp, void* h, const orc_params* pp, int N, const double* xD, const double* nD,
+                        const double* xL, const uint8_t* len, const uint8_t* type, const int32_t* obj1,
+                        const int32_t* tgt_prim, const double* tgt_pos, const int8_t* tgt_status, int max_trials,
+                        int repeats, uint64_t seed, int32_t* trials, double* inv_prob, int8_t* truncated,
+                        double* pn_out, int nthreads) {
+  const Scene& s = *(Scene*)sp;
+  const STree& t = *(STree*)h;
+  Params p = to_params(pp);
+  parallel_for(N, nthreads, [&](int c) {
+    trials[c] = 0;
+    inv_prob[c] = 0.0;
+    truncated[c] = 0;
+    pn_out[c] = 0.0;
+    int n = len[c];
+    if (tgt_status[c] != ST_CONVERGED || repeats < 1 || max_trials < 1 || n < 1 || n > KMAX) return;
+    V3d xd = get3d(xD, N, c), xl = get3d(xL, N, c), nd = get3d(nD, N, c);
+    Chain target;
+    target.n = n;
+    target.type = type[c];
+    target.xD = xd;
+    target.xL = xl;
+    for (int i = 0; i < n; ++i) {
+      V3d x(tgt_pos[((size_t)0 * KMAX + i) * N + c], tgt_pos[((size_t)1 * KMAX + i) * N + c],
+            tgt_pos[((size_t)2 * KMAX + i) * N + c]);
+      target.v[i] = make_geo(s, tgt_prim[(size_t)i * N + c], x);
+    }
+    double pn = 0.0;
+    int total = 0;
+    for (int r = 0; r < repeats; ++r) {
+      int K = max_trials;
+      bool found = false;
+      for (int k = 1; k <= max_trials && !found; ++k) {
+        uint64_t trial = 1 + (uint64_t)r * max_trials + (uint64_t)(k - 1);
+        int prim[KMAX], nn = 0, tt = 0;
+        V3d pos[KMAX];
+        if (stree_sample(s, t, p, n, obj1[c], xd, nd, xl, seed, (uint64_t)c, trial, &nn, &tt, &pn, prim, pos) != 0)
+          continue;
+        if (tt != type[c]) continue;
+        Chain start;
+        if (!load_chain(s, n, tt, xd, xl, prim, pos, &start)) continue;
+        WalkResult w;
+        walk_core(s, p, start, &w);
+        bool conv = w.status == ST_CONVERGED || w.status == ST_STALLED;
+        if (conv && chains_match(s, w.chain, target, p.match_rel * p.scale)) {
+          K = k;
+          found = true;
+        }
+      }
+      if (!found) truncated[c] = 1;
+      total += K;
+    }
+    double q[6] = {xd.x, xd.y, xd.z, xl.x, xl.y, xl.z};
+    pn = stree_pn(t, t.leaf[stree_leaf(t, q)], n);
+    pn_out[c] = pn;
+    trials[c] = total;
+    inv_prob[c] = pn > 0.0 ? (double)total / repeats / pn : 0.0;
   });
 }
 

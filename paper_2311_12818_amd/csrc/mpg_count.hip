@@ -1,58 +1,15 @@
-// Counting walk: the plain walk with every unit of work tallied (untimed; it
-// gives the algorithmic work of a launch).
-#include "mpg_internal.h"
-#include "mpg_walk.h"
-
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_walk_count(DevScene S, WalkParams P, EpView E, WalkIO io,
-                                                    unsigned long long* counts) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  Stack base = lane_stack(P.depth);
-  CountStack stk{base.base, base.depth, 0, 0, 0, 0, 0, 0, 0};
-  if (c < E.N) walk_dispatch<NMAX>(S, P, E, io, c, stk);
-  if (c < E.N) finish_dispatch<NMAX>(S, P, E, io, c, stk);
-  if (c < E.N && io.status[c] == ST_NEEDS_FP64) {
-    int n = E.len[c];
-    switch (n) {
-      case 1: fp64_one<1>(S, P, E, io, c, stk); break;
-      case 2: if (NMAX >= 2) fp64_one<(NMAX >= 2 ? 2 : 1)>(S, P, E, io, c, stk); break;
-      case 3: if (NMAX >= 3) fp64_one<(NMAX >= 3 ? 3 : 1)>(S, P, E, io, c, stk); break;
-      case 4: if (NMAX >= 4) fp64_one<(NMAX >= 4 ? 4 : 1)>(S, P, E, io, c, stk); break;
-      case 5: if (NMAX >= 5) fp64_one<(NMAX >= 5 ? 5 : 1)>(S, P, E, io, c, stk); break;
-      case 6: if (NMAX >= 6) fp64_one<(NMAX >= 6 ? 6 : 1)>(S, P, E, io, c, stk); break;
-      case 7: if (NMAX >= 7) fp64_one<(NMAX >= 7 ? 7 : 1)>(S, P, E, io, c, stk); break;
-      default: if (NMAX >= 8) fp64_one<(NMAX >= 8 ? 8 : 1)>(S, P, E, io, c, stk); break;
-    }
-  }
-  if (c < E.N) {
-    atomicAdd(&counts[0], (unsigned long long)stk.nbox);
-    atomicAdd(&counts[1], (unsigned long long)stk.ntri);
-    atomicAdd(&counts[2], (unsigned long long)stk.nsph);
-    atomicAdd(&counts[3], (unsigned long long)stk.nray);
-    atomicAdd(&counts[4], (unsigned long long)stk.nvc);
-    atomicAdd(&counts[5], (unsigned long long)stk.nvj);
-    atomicAdd(&counts[6], (unsigned long long)stk.nvj64);
-    atomicAdd(&counts[7], 1ULL);
-  }
-}
+// Counting walk: entry point (the kernels are instantiated in mpg_count_*.hip).
+#include "mpg_count.h"
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ULL;
 }
 
-typedef void (*count_kernel_t)(DevScene, WalkParams, EpView, WalkIO, unsigned long long*);
 static count_kernel_t count_kernel(int nmax) {
-  switch (nmax) {
-    case 1: return k_walk_count<1>;
-    case 2: return k_walk_count<2>;
-    case 3: return k_walk_count<3>;
-    case 4: return k_walk_count<4>;
-    case 5: return k_walk_count<5>;
-    case 6: return k_walk_count<6>;
-    case 7: return k_walk_count<7>;
-    default: return k_walk_count<8>;
-  }
+  if (nmax <= 5) return count_kernel_1to5(nmax);
+  if (nmax <= 7) return count_kernel_6to7(nmax);
+  return count_kernel_8();
 }
 extern "C" mpg_status mpg_walk_count(const mpg_scene* s, const mpg_walk_params* p, const mpg_endpoints* ep,
                                      const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,

@@ -163,7 +163,8 @@ struct DevScene {
   const int2* obj_info;     // [n_objects] (material, ior as float bits)
   const float4* spheres;    // [n_spheres] centre, radius
   const int* sphere_obj;    // [n_spheres]
-  const float* cdf;         // area prefix sums, one run per object and one over all objects
+  const float2* cdf;        // area prefix sums as unevaluated FP32 pairs (hi + lo), one run per object
+                            // and one over all objects
   const int* cdf_prim;
   const int2* cdf_range;    // [n_objects + 1] (start, count)
   const float4* obj_bounds; // [n_objects] (lo_x, lo_y, hi_x, hi_y)
@@ -1062,14 +1063,26 @@ __device__ __forceinline__ bool p0_point(const DevScene& S, const WalkParams& P,
   if (key > S.n_objects) return false;
   int2 rg = S.cdf_range[key];
   if (rg.y <= 0) return false;
-  const float* cdf = S.cdf + rg.x;
-  float total = cdf[rg.y - 1];
-  if (!(total > 0.0f)) return false;
-  float target = u1 * total;
+  // Inverse CDF in pair arithmetic (Dekker's exact product and Knuth's
+  // two-sum, FP32 operations only): a prefix sum of ~10^5 triangle areas needs
+  // about 40 significant bits to place the target between two neighbouring
+  // prefixes as exactly as an FP64 evaluation would, which one FP32 value
+  // cannot hold.
+  const float2* cdf = S.cdf + rg.x;
+  const float2 total = cdf[rg.y - 1];
+  if (!(total.x > 0.0f)) return false;
+  float th = u1 * total.x;
+  float tl = fmaf(u1, total.x, -th) + u1 * total.y;
+  {
+    float s = th + tl;
+    tl = tl - (s - th);
+    th = s;
+  }
   int lo = 0, hi = rg.y;  // first index with cdf > target
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    if (cdf[mid] > target) hi = mid;
+    float2 c = cdf[mid];
+    if (c.x > th || (c.x == th && c.y > tl)) hi = mid;
     else lo = mid + 1;
   }
   if (lo >= rg.y) lo = rg.y - 1;

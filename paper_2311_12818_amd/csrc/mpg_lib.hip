@@ -150,7 +150,8 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     zmax = std::max(zmax, d->spheres[4 * k + 2] + d->spheres[4 * k + 3]);
   }
   // area prefix sums per object and over all objects (input order), summed in
-  // FP64 on the host and stored as their FP32 roundings
+  // FP64 on the host and stored as FP32 pairs hi + lo (hi the rounding, lo
+  // the rounded remainder)
   int O = d->n_objects;
   std::vector<std::vector<double>> cd(O + 1);
   std::vector<std::vector<int>> cp(O + 1);
@@ -185,12 +186,15 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     ob[o].x = std::min(ob[o].x, sph[k].x - sph[k].w); ob[o].y = std::min(ob[o].y, sph[k].y - sph[k].w);
     ob[o].z = std::max(ob[o].z, sph[k].x + sph[k].w); ob[o].w = std::max(ob[o].w, sph[k].y + sph[k].w);
   }
-  std::vector<float> cdf;
+  std::vector<float2> cdf;
   std::vector<int> cprim;
   std::vector<int2> crange(O + 1);
   for (int k = 0; k <= O; ++k) {
     crange[k] = make_int2((int)cdf.size(), (int)cd[k].size());
-    for (double c : cd[k]) cdf.push_back((float)c);
+    for (double c : cd[k]) {
+      float hi = (float)c;
+      cdf.push_back(make_float2(hi, (float)(c - (double)hi)));
+    }
     cprim.insert(cprim.end(), cp[k].begin(), cp[k].end());
   }
   if ((e = upload(s->allocs, &D.nodes, (const float4*)nodes.data(), nodes.size() / 4)) != hipSuccess) return bail(e, "nodes");

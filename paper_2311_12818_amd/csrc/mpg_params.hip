@@ -143,16 +143,17 @@ __global__ void __launch_bounds__(256) k_refit(int n_nodes, const int32_t* range
   }
 }
 
-// per-object area prefix sums in FP32 (one thread per run, the builder's
-// order), accumulated with Kahan's compensated summation so that every
-// prefix is the FP32 rounding of the exact running sum to within an ulp or two
+// per-object area prefix sums (one thread per run, the builder's order) as
+// FP32 pairs hi + lo: each area is added with Knuth's two-sum, whose rounding
+// error goes into lo, and the pair is renormalized, so the prefixes carry
+// about 48 significant bits
 __global__ void k_area_cdf(int n_runs, const int2* range, const int* cdf_prim, const int4* tri_idx,
-                           const float4* vpos, const float4* spheres, float* cdf, const int32_t* err) {
+                           const float4* vpos, const float4* spheres, float2* cdf, const int32_t* err) {
   if (*err != MPG_OK) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_runs) return;
   int2 rg = range[r];
-  float acc = 0.0f, comp = 0.0f;
+  float hi = 0.0f, lo = 0.0f;
   for (int i = 0; i < rg.y; ++i) {
     int p = cdf_prim[rg.x + i];
     float area;
@@ -168,11 +169,13 @@ __global__ void k_area_cdf(int n_runs, const int2* range, const int* cdf_prim, c
       float rad = spheres[-1 - p].w;
       area = 4.0f * (float)M_PI * rad * rad;
     }
-    float y = area - comp;
-    float t = acc + y;
-    comp = (t - acc) - y;
-    acc = t;
-    cdf[rg.x + i] = acc;
+    float s = hi + area;
+    float bb = s - hi;
+    float e = (hi - (s - bb)) + (area - bb);
+    lo += e;
+    hi = s + lo;
+    lo = lo - (hi - s);
+    cdf[rg.x + i] = make_float2(hi, lo);
   }
 }
 
@@ -208,7 +211,7 @@ extern "C" mpg_status mpg_scene_set_params(mpg_scene* s, const float* d_theta, i
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_area_cdf, dim3((s->n_objects + 1 + 63) / 64), dim3(64), 0, stream, s->n_objects + 1,
-                     D.cdf_range, D.cdf_prim, D.tri_idx, D.vpos, D.spheres, (float*)D.cdf,
+                     D.cdf_range, D.cdf_prim, D.tri_idx, D.vpos, D.spheres, (float2*)D.cdf,
                      (const int32_t*)s->param_err);
   HIP_TRY(hipGetLastError());
   return MPG_OK;

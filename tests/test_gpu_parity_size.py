@@ -1,0 +1,334 @@
+"""GPU parity at the benchmark's sizes and launch configuration, FP64
+admissibility of every chain the GPU reports converged, Bernoulli trials on
+multi-vertex chains and with a full-resolution guide, and constructed
+edge cases whose statuses must match the oracle's."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests import gpu_common as GC
+from tests import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mpg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_2311_12818_amd as M
+    M.lib()
+    return M
+
+
+def tuned_params(M, workload, scale, **kw):
+    """The autotuned launch knobs the benchmark runs with."""
+    t = json.load(open(os.path.join(ROOT, "paper_2311_12818_amd", "tuned.json")))[workload]
+    knobs = dict(form=M.FORM_PERSISTENT, bucketing=int(t["bucketing"]), refill=int(t["refill"]),
+                 waves_per_group=int(t["waves_per_group"]), stack_depth=int(t["stack_depth"]))
+    if "length_order" in t:
+        knobs["length_order"] = M.pack_length_order(t["length_order"])
+    knobs.update(kw)
+    return M.walk_params(scale, **knobs)
+
+
+def gpu_walk(M, scene, prm, ep, prim, pos, st, ws=None):
+    import torch
+    dep = M.Endpoints(ep)
+    p, q, outs = M.manifold_walk_batch(scene, prm, dep, torch.as_tensor(prim).cuda(), torch.as_tensor(pos).cuda(),
+                                       torch.as_tensor(st).cuda(), ws=ws)
+    torch.cuda.synchronize()
+    g = {k: GC.to_np(v) for k, v in outs.items()}
+    g["prim"] = GC.to_np(p)
+    g["pos"] = GC.to_np(q).astype(np.float64)
+    g["sol"] = g["sol"].view(np.uint64)
+    return g
+
+
+def assert_gpu_chains_admissible(osc, ep, g, scale, prm_o, tag, budget=1e-3):
+    """Every chain the GPU reports converged, re-checked in FP64 at the GPU's
+    own vertices: it polishes to a residual below 1e-10 without moving more
+    than the vertex tolerance, and the polished chain passes the side and
+    visibility tests.  At most `budget` of them may fail (the parity bar's
+    0.1%: an FP32 walk that settles within rounding of a triangle edge, where
+    interpolated normals kink, can pass the FP32 tests there)."""
+    conv = g["status"] == 0
+    idx = np.nonzero(conv)[0]
+    sub = ep.subset(idx)
+    v = O.validate(osc, sub, g["prim"][:, idx], g["pos"][:, :, idx], prm=prm_o)
+    good = (v["ok"] == 1) & (v["residual"] < 1e-10) & (v["moved"] <= 1e-4 * scale) & (v["side"] == 1) & \
+           (v["visible"] == 1)
+    stats = dict(tag=tag, converged=int(conv.sum()), admissible=float(good.mean()),
+                 max_moved=float(v["moved"][v["ok"] == 1].max()), n_bad=int((~good).sum()),
+                 bad_load=int((v["ok"] == 0).sum()), bad_residual=int(((v["ok"] == 1) & (v["residual"] >= 1e-10)).sum()),
+                 bad_moved=int((v["moved"] > 1e-4 * scale).sum()), bad_side=int((v["side"] == 0).sum()),
+                 bad_visible=int((v["visible"] == 0).sum()))
+    print(stats, flush=True)
+    assert (~good).sum() <= max(1, budget * len(idx)), stats
+    return stats
+
+
+def test_headline_knobs_at_2_20_slab_chains(mpg):
+    M = mpg
+    n = 1 << 20
+    sc = W.slab_stack_scene()
+    ep = W.slab_uneven_endpoints(n, seed=5)
+    print(dict(case="headline knobs", n=n), flush=True)
+    osc = O.Scene(sc)
+    prm_o = O.params(sc.scale, cone_cos=GC.cone_cos())
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    scene = M.Scene(sc)
+    prm = tuned_params(M, "slab_uneven", sc.scale, cone_cos=GC.cone_cos())
+    ws = M.Workspace(n)
+    g = gpu_walk(M, scene, prm, ep, prim, pos, st, ws=ws)
+    o = O.walk(osc, ep, prim, pos, st, prm=prm_o)
+    GC.compare_walks(ep, g, o, sc.scale, tag="slab 2^20 tuned")
+    assert_gpu_chains_admissible(osc, ep, g, sc.scale, prm_o, "slab 2^20 tuned")
+    # the GPU's own seeds through the same launch: same seeds as the oracle's
+    import torch
+    dep = M.Endpoints(ep)
+    gp, gq, gs = M.sample_seeds(scene, dep, prm, ws=ws)
+    torch.cuda.synchronize()
+    gs = GC.to_np(gs)
+    assert (gs != st).mean() <= 1e-3
+
+
+def test_icosphere_full_2_20(mpg):
+    M = mpg
+    n = 1 << 20
+    sc = W.icosphere_glass_scene()
+    ep = W.icosphere_endpoints(n)
+    print(dict(case="icosphere", n=n), flush=True)
+    osc = O.Scene(sc)
+    prm_o = O.params(sc.scale)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    scene = M.Scene(sc)
+    prm = M.walk_params(sc.scale, max_len=2, form=M.FORM_PERSISTENT, bucketing=1, refill=1)
+    ws = M.Workspace(n)
+    g = gpu_walk(M, scene, prm, ep, prim, pos, st, ws=ws)
+    o = O.walk(osc, ep, prim, pos, st, prm=prm_o)
+    GC.compare_walks(ep, g, o, sc.scale, tag="icosphere 2^20")
+    assert_gpu_chains_admissible(osc, ep, g, sc.scale, prm_o, "icosphere 2^20")
+
+
+def test_sphere_mirror_admissible(mpg):
+    M = mpg
+    sc = W.sphere_mirror_scene()
+    ep = W.sphere_mirror_endpoints(4096)
+    osc = O.Scene(sc)
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    scene = M.Scene(sc)
+    g = gpu_walk(M, scene, M.walk_params(sc.scale, max_len=1), ep, prim, pos, st)
+    assert_gpu_chains_admissible(osc, ep, g, sc.scale, O.params(sc.scale), "sphere mirror")
+
+
+# ---------------------------------------------------------------------------
+# Bernoulli trials on multi-vertex chains and with a 32^3 guide
+# ---------------------------------------------------------------------------
+
+def test_inv_prob_slab_lengths_2_to_4(mpg):
+    import torch
+    M = mpg
+    sc = W.slab_stack_scene()
+    n = 3000
+    ep = W.slab_adjoint_endpoints(n, seed=8)
+    osc = O.Scene(sc)
+    prm_o = O.params(sc.scale, cone_cos=GC.cone_cos())
+    prim, pos, st = GC.oracle_seeds(osc, ep)
+    o = O.walk(osc, ep, prim, pos, st, prm=prm_o)
+    t_o, ip_o, tr_o = O.inv_prob(osc, ep, o["prim"], o["pos"], o["status"], max_trials=32, alpha=1.0, prm=prm_o)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    tprim = torch.as_tensor(o["prim"]).cuda()
+    tpos = torch.as_tensor(o["pos"].astype(np.float32)).cuda()
+    tst = torch.as_tensor(o["status"]).cuda()
+    plain = M.walk_params(sc.scale, max_len=4, cone_cos=GC.cone_cos())
+    pers = M.walk_params(sc.scale, max_len=4, cone_cos=GC.cone_cos(), form=M.FORM_PERSISTENT, bucketing=1, refill=1)
+    ws = M.Workspace(n)
+    a = M.estimate_inv_prob(scene, plain, dep, tprim, tpos, tst, max_trials=32, alpha=1.0)
+    b = M.estimate_inv_prob(scene, pers, dep, tprim, tpos, tst, max_trials=32, alpha=1.0, ws=ws)
+    torch.cuda.synchronize()
+    a = [GC.to_np(x) for x in a]
+    b = [GC.to_np(x) for x in b]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    conv = o["status"] == O.CONVERGED
+    agree = (a[0][conv] == t_o[conv]).mean()
+    per_len = {int(k): float((a[0][conv & (ep.length == k)] == t_o[conv & (ep.length == k)]).mean())
+               for k in (2, 3, 4)}
+    print(dict(n_conv=int(conv.sum()), K_agree=float(agree), per_len=per_len, mean_g=float(a[0][conv].mean()),
+               mean_o=float(t_o[conv].mean())), flush=True)
+    assert conv.sum() > 1000
+    assert agree >= 0.98
+    assert abs(a[0][conv].mean() - t_o[conv].mean()) <= 0.03 * t_o[conv].mean()
+
+
+def synth_samples(n, lo, hi, seed=0):
+    g = np.random.default_rng(seed)
+    xD = g.uniform(lo, hi, (n, 3))
+    k = g.integers(0, 3, n)
+    cen = np.array([[0.5, 0.5], [2.5, 1.0], [1.5, 3.0]])[k] + 0.2 * xD[:, :2]
+    uv = cen + g.normal(scale=0.08 + 0.04 * k[:, None], size=(n, 2))
+    w = g.uniform(0.1, 2.0, n)
+    return np.concatenate([xD, uv, w[:, None], np.zeros((n, 2))], 1).astype(np.float32)
+
+
+def test_guided_seeds_and_trials_with_a_32_cubed_guide(mpg):
+    import torch
+    M = mpg
+    sc = W.water_scene()
+    osc = O.Scene(sc)
+    lo, hi = np.array(W.WATER_GRID_LO), np.array(W.WATER_GRID_HI)
+    og = O.fit_guide(synth_samples(1 << 20, lo, hi, seed=4), lo, hi, res=32, scale=4.0)
+    assert og.valid.sum() > 0.9 * 32 ** 3
+    ep = W.water_endpoints(8192, seed=9)
+    oprim, opos, ost = O.sample_seeds(osc, ep, guide=og, alpha=0.5)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    gd = M.Guide(lo, hi, res=32, scale=4.0)
+    gd.upload(og.valid, og.pi, og.mu, og.cov)
+    prm = M.walk_params(sc.scale, max_len=1)
+    prim, pos, st = M.sample_seeds(scene, dep, prm, alpha=0.5, guide=gd)
+    torch.cuda.synchronize()
+    gprim, gpos, gst = GC.to_np(prim), GC.to_np(pos), GC.to_np(st)
+    ok = (gst == 0) & (ost == 0)
+    err = np.abs(gpos[:, 0, :] - opos[:, 0, :]).max(0)
+    close = ok & (gprim[0] == oprim[0]) & (err <= 1e-4 * sc.scale)
+    frac = (np.sum(gst != ost) + np.sum(ok & ~close)) / ep.n
+    print(dict(seed_mismatch=float(frac)), flush=True)
+    assert frac <= 1e-3
+    # trials with the same guide
+    o = O.walk(osc, ep, oprim, opos.astype(np.float32), ost)
+    n2 = 2048
+    sub = ep.subset(np.arange(n2))
+    t_o, _, _ = O.inv_prob(osc, sub, o["prim"][:, :n2], o["pos"][:, :, :n2], o["status"][:n2], max_trials=64,
+                           guide=og, alpha=0.5)
+    dsub = M.Endpoints(sub)
+    t_g, _, _ = M.estimate_inv_prob(scene, prm, dsub, torch.as_tensor(np.ascontiguousarray(o["prim"][:, :n2])).cuda(),
+                                    torch.as_tensor(np.ascontiguousarray(o["pos"][:, :, :n2]).astype(np.float32)).cuda(),
+                                    torch.as_tensor(np.ascontiguousarray(o["status"][:n2])).cuda(), max_trials=64,
+                                    alpha=0.5, guide=gd)
+    torch.cuda.synchronize()
+    t_g = GC.to_np(t_g)
+    conv = o["status"][:n2] == O.CONVERGED
+    agree = (t_g[conv] == t_o[conv]).mean()
+    print(dict(n_conv=int(conv.sum()), K_agree=float(agree)), flush=True)
+    assert conv.sum() > 100 and agree >= 0.98
+
+
+# ---------------------------------------------------------------------------
+# constructed edge cases: statuses must match the oracle's
+# ---------------------------------------------------------------------------
+
+def blocker_scene():
+    """Mirror plane z = 0 over [-2, 2]^2 (object 0) and a mirror blocker
+    z = 1.5 over [0.5, 2] x [-2, 2] facing down (object 1)."""
+    v = np.array([[-2, -2, 0], [2, -2, 0], [2, 2, 0], [-2, 2, 0],
+                  [0.5, -2, 1.5], [2, -2, 1.5], [2, 2, 1.5], [0.5, 2, 1.5]], np.float64)
+    t = np.array([[0, 1, 2], [0, 2, 3], [4, 6, 5], [4, 7, 6]])
+    n = np.array([[0, 0, 1.0]] * 4 + [[0, 0, -1.0]] * 4)
+    return W._finish("blocker", v, n, t, np.array([0, 0, 1, 1]), [W.MAT_MIRROR, W.MAT_MIRROR], [1.0, 1.0],
+                     np.zeros((0, 4)), [], 4.0)
+
+
+def forced_case(name):
+    g = np.random.default_rng(61)
+    if name == "occluded_light":
+        sc = blocker_scene()
+        N = 2048
+        xD = np.stack([g.uniform(-1.8, 0.0, N), g.uniform(-1.5, 1.5, N), g.uniform(0.2, 1.0, N)], 1)
+        xL = np.stack([g.uniform(0.6, 1.9, N), g.uniform(-1.5, 1.5, N), g.uniform(2.0, 3.0, N)], 1)
+        return sc, S.endpoints(xD, xL, obj1=0)
+    if name == "xD_equals_xL":
+        sc = W.sphere_mirror_scene()
+        N = 1024
+        x = np.stack([g.uniform(-1.5, 1.5, N), g.uniform(-1.5, 1.5, N), g.uniform(1.5, 3.0, N)], 1)
+        return sc, S.endpoints(x, x, nD=(0, 0, -1), obj1=0)
+    if name == "grazing":
+        sc = S.plane_scene(W.MAT_MIRROR, half=4.0)
+        N = 2048
+        xD = np.stack([g.uniform(-3.8, -3.0, N), g.uniform(-1, 1, N), g.uniform(0.005, 0.05, N)], 1)
+        xL = np.stack([g.uniform(3.0, 3.8, N), g.uniform(-1, 1, N), g.uniform(0.005, 0.05, N)], 1)
+        return sc, S.endpoints(xD, xL, obj1=0)
+    if name == "tir_seeds":
+        sc = W.slab_stack_scene(amp=0.0)
+        N = 4096
+        n = g.integers(2, 9, N)
+        zs = np.array([W.interface_z(k) - 0.5 * W.SLAB_THICK for k in range(1, 9)])
+        xD = np.stack([g.uniform(1.0, 3.0, N), g.uniform(1.0, 3.0, N), zs[n - 1]], 1)
+        return sc, S.endpoints(xD, np.tile([2.0, 2.0, 3.0], (N, 1)), n=n, types=(1 << n) - 1, obj1=W.P0_DIRECTION)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["occluded_light", "xD_equals_xL", "grazing", "tir_seeds"])
+def test_forced_statuses_match_oracle(mpg, name):
+    import torch
+    M = mpg
+    sc, ep = forced_case(name)
+    print(dict(case=name, n=ep.n), flush=True)
+    cone = math.cos(math.radians(65.0)) if name == "tir_seeds" else 0.0
+    osc = O.Scene(sc)
+    prm_o = O.params(sc.scale, cone_cos=cone)
+    oprim, opos, ost = O.sample_seeds(osc, ep, prm=prm_o)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    prm = M.walk_params(sc.scale, cone_cos=cone, max_len=int(ep.length.max()))
+    gprim, gpos, gst = M.sample_seeds(scene, dep, prm)
+    torch.cuda.synchronize()
+    gst = GC.to_np(gst)
+    assert (gst != ost).mean() <= 1e-3, (gst != ost).mean()
+    g = gpu_walk(M, scene, prm, ep, oprim, opos.astype(np.float32), ost)
+    o = O.walk(osc, ep, oprim, opos.astype(np.float32), ost, prm=prm_o)
+    hist_g = np.bincount(g["status"].astype(np.int64), minlength=9)
+    hist_o = np.bincount(o["status"].astype(np.int64), minlength=9)
+    print(dict(case=name, gpu=hist_g.tolist(), oracle=hist_o.tolist()), flush=True)
+    if name == "grazing":
+        # reflections within 0.3-3 degrees of grazing: the FP32 half vector
+        # loses about eps / cos(theta) ~ 1e-5 of its direction, the size of
+        # the residual tolerance, so FP32 walks and the FP64 walk end
+        # differently on some chains.  Every chain the GPU accepts must be
+        # admissible in FP64, and most of the oracle's must be found.
+        gc, oc = g["status"] == 0, o["status"] == 0
+        assert_gpu_chains_admissible(osc, ep, g, sc.scale, prm_o, name, budget=0.0)
+        assert (gc & oc).sum() >= 0.75 * oc.sum()
+        return
+    assert (g["status"] != o["status"]).mean() <= 2e-3
+    expect = {"occluded_light": O.OCCLUDED, "tir_seeds": O.SEED_INVALID}
+    if name in expect:
+        assert hist_o[expect[name]] > 20
+    if (o["status"] == 0).sum() > 0:
+        GC.compare_walks(ep, g, o, sc.scale, min_conv=1, tag=name)
+
+
+@pytest.mark.parametrize("max_trials", [0, 1])
+def test_trial_caps_zero_and_one(mpg, max_trials):
+    import torch
+    M = mpg
+    sc = W.water_scene()
+    osc = O.Scene(sc)
+    ep = W.water_endpoints(2048, seed=13)
+    oprim, opos, ost = O.sample_seeds(osc, ep)
+    o = O.walk(osc, ep, oprim, opos.astype(np.float32), ost)
+    t_o, ip_o, tr_o = O.inv_prob(osc, ep, o["prim"], o["pos"], o["status"], max_trials=max_trials, alpha=1.0)
+    scene = M.Scene(sc)
+    dep = M.Endpoints(ep)
+    prm = M.walk_params(sc.scale, max_len=1)
+    t_g, ip_g, tr_g = M.estimate_inv_prob(scene, prm, dep, torch.as_tensor(o["prim"]).cuda(),
+                                          torch.as_tensor(o["pos"].astype(np.float32)).cuda(),
+                                          torch.as_tensor(o["status"]).cuda(), max_trials=max_trials, alpha=1.0)
+    torch.cuda.synchronize()
+    t_g, tr_g = GC.to_np(t_g), GC.to_np(tr_g)
+    conv = o["status"] == O.CONVERGED
+    if max_trials == 0:
+        assert np.all(t_g == 0) and np.all(t_o == 0)
+    else:
+        assert np.all(t_g[conv] == 1) and np.all(t_o[conv] == 1)
+        assert (tr_g[conv] != tr_o[conv]).mean() <= 0.02

@@ -384,3 +384,51 @@ def test_ball_lens_mean_inverse_probability_counts_three_chains(oracle_lib):
     est = np.where(r["status"] == O.CONVERGED, ip, 0.0)
     se = est.std() / math.sqrt(M)
     assert abs(est.mean() - 3.0) < 4 * se, (est.mean(), se)
+
+
+# ---------------------------------------------------------------------------
+# validation of external chains (used on the GPU's converged chains)
+# ---------------------------------------------------------------------------
+
+def test_validate_accepts_float32_solutions_and_rejects_wrong_type(oracle_lib):
+    eta = 1.5
+    sc = S.plane_scene(W.MAT_DIELECTRIC, ior=eta)
+    osc = O.Scene(sc)
+    g = np.random.default_rng(14)
+    N = 200
+    xD = np.stack([g.uniform(-1.5, 1.5, N), g.uniform(-1.5, 1.5, N), g.uniform(-2, -0.3, N)], 1)
+    xL = np.stack([g.uniform(-1.5, 1.5, N), g.uniform(-1.5, 1.5, N), g.uniform(0.5, 3, N)], 1)
+    ep = ep64(xD, xL, n=1, types_=1)
+    prim, pos, st = O.sample_seeds(osc, ep)
+    r = O.walk(osc, ep, prim, pos.astype(np.float32), st)
+    conv = r["status"] == O.CONVERGED
+    assert conv.sum() > 50
+    pos32 = r["pos"].astype(np.float32).astype(np.float64)
+    v = O.validate(osc, ep, r["prim"], pos32)
+    assert np.all(v["ok"][conv] == 1)
+    assert v["residual"][conv].max() < 1e-10
+    assert v["moved"][conv].max() < 1e-5
+    assert np.all(v["side"][conv] == 1) and np.all(v["visible"][conv] == 1)
+    for c in np.nonzero(conv)[0]:
+        assert np.linalg.norm(pos32[:, 0, c] + 0 - snell_point_flat(xD[c], xL[c], eta)) < 1e-6
+    # the same vertices read as a reflection: the polish moves them far (or
+    # the side test fails), so the chain is not accepted as an R solution
+    ep_r = ep64(xD, xL, n=1, types_=0)
+    w = O.validate(osc, ep_r, r["prim"], pos32)
+    bad = (w["residual"] > 1e-10) | (w["moved"] > 1e-4 * sc.scale) | (w["side"] == 0)
+    assert np.all(bad[conv])
+
+
+def snell_point_flat(xD, xL, eta):
+    """Refraction point on z = 0 by bisection on Snell's law in the plane of incidence."""
+    dh = xL[:2] - xD[:2]
+    D = np.linalg.norm(dh)
+    u = dh / D
+    hD, hL = abs(xD[2]), abs(xL[2])
+    a, b = 0.0, D
+    for _ in range(200):
+        m = 0.5 * (a + b)
+        f = eta * m / math.hypot(m, hD) - (D - m) / math.hypot(D - m, hL)
+        a, b = (m, b) if f < 0 else (a, m)
+    s = 0.5 * (a + b)
+    return np.array([xD[0] + u[0] * s, xD[1] + u[1] * s, 0.0])
