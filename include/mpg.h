@@ -277,6 +277,24 @@ mpg_status manifold_walk_batch(const mpg_scene* scene, const mpg_walk_params* pa
                                const mpg_chains* seeds, const int8_t* d_seed_status, mpg_chains* out,
                                const mpg_walk_out* wout, mpg_workspace* ws, void* hip_stream);
 
+/* Allocation-free manifold_walk_batch, for callers that cannot allocate
+ * device memory or create streams: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * and kernels as manifold_walk_batch, without a workspace: the persistent
+ * form keeps its bucket order, queue heads and per-chain class bytes in a
+ * static device array of about 5.3 MB per device (held until the process
+ * ends), and every per-length kernel runs on hip_stream.  Limits: N <=
+ * MPG_NOALLOC_MAX_CHAINS (else MPG_ERR_INVALID_ARG); bucketing 0 or 1 in the
+ * persistent form (2 and 3 need a workspace: MPG_ERR_UNSUPPORTED).  Every
+ * call on one device shares that array, which keeps the last call's
+ * contents (each call resets what it reads first): calls that overlap on one
+ * device, on different streams or host threads, race and must not be
+ * issued. */
+#define MPG_NOALLOC_MAX_CHAINS (1 << 20)
+mpg_status manifold_walk_batch_noalloc(const mpg_scene* scene, const mpg_walk_params* params,
+                                       const mpg_endpoints* ep, const mpg_chains* seeds, const int8_t* d_seed_status,
+                                       mpg_chains* out, const mpg_walk_out* wout, void* hip_stream);
+
 /* FP64 pass of the walk (normally run by manifold_walk_batch itself): chains
  * whose status is MPG_NEEDS_FP64 (converged in FP32 but near-singular, stalled
  * at the FP32 residual floor, or scattering within fp64_graze_cos of grazing)

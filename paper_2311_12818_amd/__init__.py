@@ -107,6 +107,9 @@ def lib():
                                         C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, F32, P, P, P, P, P]
         L.fit_guide.argtypes = [P, P, I32, P, P, P]
         L.make_guide_samples.argtypes = [C.POINTER(mpg_endpoints), C.POINTER(mpg_chains), P, P, P, P, P, P]
+        L.manifold_walk_batch_noalloc.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                                  C.POINTER(mpg_chains), P, C.POINTER(mpg_chains),
+                                                  C.POINTER(mpg_walk_out), P]
         L.manifold_walk_fp64.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                          C.POINTER(mpg_chains), C.POINTER(mpg_walk_out), P]
         L.mpg_walk_count.argtypes = [P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.POINTER(mpg_chains),
@@ -117,7 +120,7 @@ def lib():
                      "mpg_guide_create", "mpg_guide_upload", "mpg_guide_download", "sample_seeds",
                      "manifold_walk_batch", "estimate_inv_prob", "fit_guide", "manifold_walk_adjoint",
                      "manifold_walk_fp64", "mpg_walk_count", "make_guide_samples", "mpg_scene_set_params",
-                     "mpg_scene_params_error"]:
+                     "mpg_scene_params_error", "manifold_walk_batch_noalloc"]:
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -360,6 +363,22 @@ def manifold_walk_batch(scene: Scene, params: mpg_walk_params, ep: Endpoints, se
     _check(lib().manifold_walk_batch(scene.h, C.byref(params), C.byref(ep.c()), C.byref(seeds), _ptr(seed_status),
                                      C.byref(oc), C.byref(wo), ws.h if ws else None, _stream()),
            "manifold_walk_batch")
+    return out_prim, out_pos, outs
+
+
+NOALLOC_MAX_CHAINS = 1 << 20
+
+
+def manifold_walk_batch_noalloc(scene: Scene, params: mpg_walk_params, ep: Endpoints, seed_prim, seed_pos,
+                                seed_status=None, out_prim=None, out_pos=None, outs=None):
+    """manifold_walk_batch without a workspace (allocation-free entry point;
+    see manifold_walk_batch_noalloc in mpg.h).  The caller passes every
+    input and output; returns (prim, pos, outputs dict)."""
+    seeds = mpg_chains(seed_prim.data_ptr(), seed_pos.data_ptr())
+    oc = mpg_chains(out_prim.data_ptr(), out_pos.data_ptr())
+    _check(lib().manifold_walk_batch_noalloc(scene.h, C.byref(params), C.byref(ep.c()), C.byref(seeds),
+                                             _ptr(seed_status), C.byref(oc), C.byref(_wout(outs)), _stream()),
+           "manifold_walk_batch_noalloc")
     return out_prim, out_pos, outs
 
 
