@@ -372,6 +372,139 @@ mpg_status manifold_walk_adjoint(const mpg_scene* scene, const mpg_walk_params* 
                                  const float* d_grad_G, float* d_grad_xD, float* d_grad_xL, float* d_grad_theta,
                                  mpg_workspace* ws, void* hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* The paper's guide (Sec. 5.5, 5.6): a binary tree over the 6-D              */
+/* configuration (x_D, x_L); per leaf the weighted distributions of the chain */
+/* length n and type tau (Eq. eq_div2) and a mixture of von Mises-Fisher      */
+/* lobes over w_D (Eq. vMF), one per sub-path sample.                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct mpg_stree mpg_stree;
+
+typedef struct {
+  float lo[6], hi[6];   /* root box over (x_D, x_L); samples outside it are not used */
+  float eps;            /* child overlap: a child keeps its parent's samples inside its box widened by eps times
+                           its extent along the split axis (0.1) */
+  float thr_scale;      /* a node with more than thr_scale sqrt(|S|) samples is split (1) */
+  int32_t max_depth;    /* depth limit of the tree (20) */
+  float sigma_min;      /* lower bound of a lobe's footprint angle, radians (1e-3) */
+  float sigma_lone;     /* footprint of a lobe alone in its (n, tau) group, radians (0.1) */
+  float p0n[8];         /* P_0(n), n = 1..8 (normalised by the library) */
+  float alpha;          /* probability of the initial distributions in the defensive mixtures (0.5) */
+  float p_transmit;     /* p_0's probability of transmission at a dielectric vertex (0.5) */
+} mpg_stree_desc;
+
+/* Fills the defaults noted above (root box [0, 1]^6, P_0 uniform). */
+mpg_status mpg_stree_desc_default(mpg_stree_desc* desc);
+/* Creates an empty guide (one leaf without samples: p_0 only).  Allocates
+ * device memory; synchronous. */
+mpg_status mpg_stree_create(const mpg_stree_desc* desc, mpg_stree** out);
+void mpg_stree_destroy(mpg_stree* tree);
+/* Replaces P_0(n), alpha and p_transmit (host values; takes effect for the
+ * calls issued afterwards). */
+mpg_status mpg_stree_set_prior(mpg_stree* tree, const float* p0n, float alpha, float p_transmit);
+
+/* Fits the guide to sub-path sample records d_records [n][16] float: x_D
+ * (3), x_L (3), w_D (3, unit), w, n, tau, 0 x 4 (as written by
+ * make_guide_records).  Records with w <= 0, non-finite values, n outside
+ * 1..8 or x outside the root box are ignored.  The tree is built breadth
+ * first: a node with more than thr_scale sqrt(|S|) samples is halved across
+ * its longest side; each child keeps its parent's samples inside its box
+ * widened by eps of its extent along the split axis (Sec. 5.6).  Per leaf:
+ * W, W_n; lobes grouped by (n, tau) with kappa = sigma^-2, sigma the angle to
+ * the nearest other direction of the group, computed on the GPU.  The
+ * records are copied to the host and the tree is built there: synchronous
+ * on hip_stream; reallocates the guide's device memory. */
+mpg_status fit_guide_stree(mpg_stree* tree, const float* d_records, int32_t n_records, void* hip_stream);
+
+/* Node, leaf, group and lobe counts of the fitted guide. */
+mpg_status mpg_stree_stats(const mpg_stree* tree, int32_t* n_nodes, int32_t* n_leaves, int32_t* n_groups,
+                           int32_t* n_lobes);
+/* Host copies of the guide (any pointer may be NULL): per node axis (-1 =
+ * leaf), mid, child, W, W_n [8], own samples, leaf groups (first, count);
+ * per group key (n | tau << 8), weight, lobes (first, count); per lobe
+ * (direction, kappa) [4] and the inclusive prefix of lobe weights in its
+ * group.  Synchronous. */
+mpg_status mpg_stree_download(const mpg_stree* tree, int32_t* axis, float* mid, int32_t* child, float* W, float* Wn,
+                              int32_t* own, int32_t* leaf_groups, int32_t* grp_key, float* grp_w, int32_t* grp_lobes,
+                              float* lobe, float* lobe_cdf);
+
+/* Seeds from the guide (Sec. 5.3-5.5): per configuration the leaf of (x_D,
+ * x_L); n = ep->d_len[c] when it is 1..8, else (0) drawn from alpha P_0(n) +
+ * (1 - alpha) P_e(n); then (w_D, tau) from alpha p_0 + (1 - alpha) p_e: p_0
+ * takes x_1 by ep->d_obj1 and decides tau at each vertex as the ray reaches
+ * it (a mirror reflects, a dielectric transmits with p_transmit); p_e draws
+ * tau from P_e(tau | n), a lobe by weight and w_D from the lobe; x_2..x_n
+ * follow by Eq. (deduction).  ep->d_type is not read.  Outputs: n
+ * (d_len_out), tau (d_type_out), P(n) of the mixture (d_pn), the seed chain
+ * and d_status (0, MPG_SEED_INVALID or MPG_BAD_INPUT).  Random numbers:
+ * Philox4x64-10, key (philox_seed, 0), counters (chain, trial, 0..2, 0). */
+mpg_status sample_seeds_stree(const mpg_scene* scene, const mpg_stree* tree, const mpg_walk_params* params,
+                              const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, uint8_t* d_len_out,
+                              uint8_t* d_type_out, float* d_pn, mpg_chains* out, int8_t* d_status,
+                              void* hip_stream);
+
+/* Reciprocal probability with the guide (Sec. 5.8): for each target with
+ * status MPG_CONVERGED, n = ep->d_len is kept and each trial draws (w_D,
+ * tau) from the same mixture as sample_seeds_stree (trial counters 1 + r
+ * max_trials + k - 1) and walks it; a trial matches when its tau equals
+ * ep->d_type and its chain the target (same objects, vertices within
+ * match_rel L).  d_trials = sum_r K_r, d_pn = P(n), d_inv_prob = mean_r K_r /
+ * P(n) (P(n) factored out of the estimate).  Other targets get 0. */
+mpg_status estimate_inv_prob_stree(const mpg_scene* scene, const mpg_stree* tree, const mpg_walk_params* params,
+                                   const mpg_endpoints* ep, const mpg_chains* target, const int8_t* d_target_status,
+                                   int32_t max_trials, int32_t repeats, uint64_t philox_seed, int32_t* d_trials,
+                                   float* d_inv_prob, uint8_t* d_truncated, float* d_pn, void* hip_stream);
+
+/* Sample records for fit_guide_stree from walked chains: {x_D, x_L, w_D =
+ * normalize(x_1 - x_D), w, n, tau, 0 x 4} with w = T <1/P> (Eq. eq_weight),
+ * T = kappa G, <1/P> = d_inv_prob; w = 0 unless d_status is MPG_CONVERGED. */
+mpg_status make_guide_records(const mpg_endpoints* ep, const mpg_chains* chains, const int8_t* d_status,
+                              const float* d_G, const float* d_kappa, const float* d_inv_prob, float* d_records,
+                              void* hip_stream);
+
+/* Selective activation (Sec. 5.8): d_active[c] = 1 when the leaf of
+ * configuration c holds own samples of the last fit (samples kept only for
+ * the child overlap do not count), else 0 (the caller falls back to path
+ * tracing there). */
+mpg_status mpg_stree_active(const mpg_stree* tree, const mpg_endpoints* ep, uint8_t* d_active, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Progressive training (Sec. 5.8): iterations with doubling sample counts,   */
+/* training stopped at a share of the budget, the guide fitted from the last  */
+/* iteration's samples only.  Host-side state machine; the caller owns the    */
+/* clock and the sample batches.                                              */
+/* ------------------------------------------------------------------------ */
+
+#define MPG_TRAIN 0
+#define MPG_RENDER 1
+
+typedef struct {
+  double budget;          /* total budget (any unit of time) */
+  double train_fraction;  /* share of the budget for training (0.3) */
+  int64_t base_samples;   /* samples of iteration 0; iteration k takes base 2^k */
+} mpg_train_plan;
+
+typedef struct {
+  int32_t phase;      /* MPG_TRAIN or MPG_RENDER */
+  int32_t iteration;  /* current training iteration */
+  int64_t target;     /* its sample count (base 2^iteration) */
+  int64_t done;       /* samples gathered in it so far */
+  int32_t refit;      /* set by mpg_train_step: fit the guide now from the samples of the iteration that
+                         just ended (then gather the next iteration's samples afresh) */
+} mpg_train_state;
+
+/* Starts training (MPG_RENDER at once when train_fraction is 0). */
+mpg_status mpg_train_init(const mpg_train_plan* plan, mpg_train_state* state);
+/* Records `batch` more samples of the current iteration at time `elapsed`
+ * (since the start of the budget) and advances the schedule: once elapsed
+ * reaches train_fraction budget, training ends (phase MPG_RENDER, refit for
+ * the last iteration); when the iteration has its target count and less than
+ * half of the training budget is used, refit and start the next iteration
+ * with twice the samples; otherwise the current iteration goes on
+ * (gathering past its target once half of the training budget is used). */
+mpg_status mpg_train_step(const mpg_train_plan* plan, mpg_train_state* state, int64_t batch, double elapsed);
+
 #ifdef __cplusplus
 }
 #endif

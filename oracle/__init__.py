@@ -65,11 +65,12 @@ def _declare(L):
     L.orc_offset_positions.restype = C.c_int
     L.orc_offset_positions.argtypes = [P, C.c_int, P, P, P, P]
     L.orc_sample_seeds.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, U64, U64, D, P, P,
-                                   P, C.c_int]
+                                   P, C.c_int, P]
+    L.orc_sample_offsets.argtypes = [C.c_int, U64, U64, D, P]
     L.orc_walk.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, C.c_int, P, P, P, P, P,
-                           P, P, P, P, C.c_int]
+                           P, P, P, P, C.c_int, P]
     L.orc_inv_prob.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, C.c_int,
-                               C.c_int, U64, D, P, P, P, C.c_int]
+                               C.c_int, U64, D, P, P, P, C.c_int, P]
     L.orc_validate.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, C.c_int]
     L.orc_scene_set_theta.restype = C.c_int
     L.orc_scene_set_theta.argtypes = [P, C.c_int, P]
@@ -211,7 +212,18 @@ def _guide_args(guide):
     return gi, gd, (gi, gd)
 
 
-def sample_seeds(osc: Scene, ep, seed=0, trial=0, alpha=0.5, guide=None, prm=None, nthreads=0):
+def _off(offsets):
+    return None if offsets is None else _c(offsets, np.float64)
+
+
+def sample_offsets(N, seed=0, trial=0, roughness=0.1):
+    """GGX offset normals (o_s, o_t) of glossy chains, [2][K][N] (Sec. 5.7)."""
+    out = np.zeros((2, KMAX, N))
+    lib().orc_sample_offsets(int(N), int(seed), int(trial), float(roughness), _p(out))
+    return out
+
+
+def sample_seeds(osc: Scene, ep, seed=0, trial=0, alpha=0.5, guide=None, prm=None, nthreads=0, offsets=None):
     N = ep.n
     prm = prm or params(osc.scale)
     gi, gd, keep = _guide_args(guide)
@@ -220,11 +232,12 @@ def sample_seeds(osc: Scene, ep, seed=0, trial=0, alpha=0.5, guide=None, prm=Non
     st = np.zeros(N, np.int8)
     lib().orc_sample_seeds(osc.h, _p(gi), _p(gd), C.byref(prm), N, _p(_c(ep.xD, np.float64)),
                            _p(_c(ep.nD, np.float64)), _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)), _p(_c(ep.obj1, np.int32)),
-                           int(seed), int(trial), float(alpha), _p(prim), _p(pos), _p(st), nthreads)
+                           int(seed), int(trial), float(alpha), _p(prim), _p(pos), _p(st), nthreads,
+                           _p(_off(offsets)))
     return prim, pos, st
 
 
-def walk(osc: Scene, ep, seed_prim, seed_pos, seed_status=None, polish=True, prm=None, nthreads=0):
+def walk(osc: Scene, ep, seed_prim, seed_pos, seed_status=None, polish=True, prm=None, nthreads=0, offsets=None):
     """Walk every chain from the given seeds (positions are taken as float32,
     widened to FP64).  Returns a dict of outputs."""
     N = ep.n
@@ -239,7 +252,7 @@ def walk(osc: Scene, ep, seed_prim, seed_pos, seed_status=None, polish=True, prm
                    _p(_c(ep.xL, np.float64)), _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)), _p(spr),
                    _p(sp), _p(ss), int(polish), _p(out["prim"]), _p(out["pos"]), _p(out["status"]),
                    _p(out["iters"]), _p(out["sol"]), _p(out["G"]), _p(out["kappa"]), _p(out["residual"]),
-                   _p(out["polished"]), nthreads)
+                   _p(out["polished"]), nthreads, _p(_off(offsets)))
     return out
 
 
@@ -260,7 +273,7 @@ def validate(osc: Scene, ep, prim, pos, prm=None, nthreads=0):
 
 
 def inv_prob(osc: Scene, ep, tgt_prim, tgt_pos, tgt_status, max_trials=64, repeats=1, seed=0, alpha=0.5,
-             guide=None, prm=None, nthreads=0):
+             guide=None, prm=None, nthreads=0, offsets=None):
     N = ep.n
     prm = prm or params(osc.scale)
     gi, gd, keep = _guide_args(guide)
@@ -271,7 +284,7 @@ def inv_prob(osc: Scene, ep, tgt_prim, tgt_pos, tgt_status, max_trials=64, repea
                        _p(_c(ep.nD, np.float64)), _p(_c(ep.xL, np.float64)), _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)),
                        _p(_c(ep.obj1, np.int32)), _p(_c(tgt_prim, np.int32)), _p(_c(tgt_pos, np.float64)),
                        _p(_c(tgt_status, np.int8)), int(max_trials), int(repeats), int(seed), float(alpha),
-                       _p(trials), _p(ip), _p(tr), nthreads)
+                       _p(trials), _p(ip), _p(tr), nthreads, _p(_off(offsets)))
     return trials, ip, tr
 
 

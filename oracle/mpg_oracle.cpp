@@ -406,9 +406,17 @@ static V3<T> geo_shading(const VGeo& g, const V3<T>& x) {
 // the ordinary half vector.  The two residual components are the projections
 // of h/|h| on the orthonormal shading tangent frame
 //   s = normalize(e1 - (e1.n_s) n_s),  t = n_s x s.
+//
+// Glossy chains (Sec. 5.7): with a sampled offset normal m = o_s s + o_t t +
+// sqrt(1 - o_s^2 - o_t^2) n_s the chain is specular about m instead of n_s,
+// i.e. h/|h|, turned to the n_s side, has the tangential components (o_s,
+// o_t): C = (sign(h.n_s) h.s - o_s, sign(h.n_s) h.t - o_t).  The offset is
+// expressed in a frame that varies smoothly across triangles: s from the
+// world x axis projected on the tangent plane (the caller passes it as e1),
+// which holds wherever n_s is away from +-x (height fields, slabs).
 template <class T>
 static void vertex_constraint(const V3<T>& xp, const V3<T>& x, const V3<T>& xn, const V3<T>& ns, const V3d& e1,
-                              double eta_a, double eta_b, T* C) {
+                              double eta_a, double eta_b, const double* off, T* C) {
   V3<T> wi = normalize(xp - x), wo = normalize(xn - x);
   V3<T> h = normalize(wi * T(eta_a) + wo * T(eta_b));
   V3<T> E1 = lift<T>(e1);
@@ -416,6 +424,21 @@ static void vertex_constraint(const V3<T>& xp, const V3<T>& x, const V3<T>& xn, 
   V3<T> t = cross(ns, s);
   C[0] = dot(h, s);
   C[1] = dot(h, t);
+  if (off) {
+    double sg = val(dot(h, ns)) < 0.0 ? -1.0 : 1.0;
+    C[0] = C[0] * T(sg) - T(off[0]);
+    C[1] = C[1] * T(sg) - T(off[1]);
+  }
+}
+
+static const V3d kGlossyRef(1.0, 0.0, 0.0);
+
+// The offset normal of a glossy vertex (Sec. 5.7) in its shading frame.
+static V3d offset_normal(const V3d& e1, const V3d& ns, const double* off) {
+  V3d s = normalize(e1 - ns * dot(e1, ns));
+  V3d t = cross(ns, s);
+  double c = std::sqrt(std::max(0.0, 1.0 - off[0] * off[0] - off[1] * off[1]));
+  return normalize(s * off[0] + t * off[1] + ns * c);
 }
 
 // Indices of refraction on the two sides of vertex g for incoming w_i.
@@ -430,6 +453,8 @@ struct Chain {
   VGeo v[KMAX];
   V3d xD, xL;
   double ea[KMAX], eb[KMAX];
+  bool glossy = false;          // offset normals given (Sec. 5.7)
+  double off[KMAX][2] = {{0}};  // per vertex (o_s, o_t)
   bool T(int i) const { return (type >> i) & 1; }
 };
 
@@ -454,7 +479,8 @@ static void chain_residual(const Chain& c, const T* y, const T& u1, const T& u2,
     ns[i] = geo_shading(c.v[i], x[i + 1]);
   }
   for (int i = 0; i < c.n; ++i)
-    vertex_constraint(x[i], x[i + 1], x[i + 2], ns[i], c.v[i].e1, c.ea[i], c.eb[i], &C[2 * i]);
+    vertex_constraint(x[i], x[i + 1], x[i + 2], ns[i], c.glossy ? kGlossyRef : c.v[i].e1, c.ea[i], c.eb[i],
+                      c.glossy ? c.off[i] : nullptr, &C[2 * i]);
 }
 
 static void residual(const Chain& c, double* C) {
@@ -682,6 +708,7 @@ static double chain_kappa(const Chain& c) {
     V3d xp = i == 0 ? c.xD : c.v[i - 1].x;
     V3d wi = normalize(xp - g.x);
     V3d ns = geo_shading<double>(g, g.x);
+    if (c.glossy) ns = offset_normal(kGlossyRef, ns, c.off[i]);
     // physical indices: incident side of w_i, transmitted side the other
     bool outside = dot(wi, g.ng) > 0.0;
     double F = fresnel_dielectric(dot(wi, ns), outside ? 1.0 : g.ior, outside ? g.ior : 1.0);
@@ -756,10 +783,14 @@ static bool finite3(const V3d& v) { return std::isfinite(v.x) && std::isfinite(v
 // Full walk of one chain: walk, (oracle) polish, side and visibility tests,
 // then G, kappa and the solution id.
 static void walk_chain(const Scene& s, const Params& p, int n, int type, const V3d& xD, const V3d& nD, const V3d& xL,
-                       const int* prim, const V3d* pos, bool do_polish, WalkResult* res) {
+                       const int* prim, const V3d* pos, bool do_polish, WalkResult* res, const double* offs = nullptr) {
   Chain c;
   if (!finite3(xD) || !finite3(xL) || n < 1 || n > KMAX) { res->status = ST_BAD_INPUT; return; }
   if (!load_chain(s, n, type, xD, xL, prim, pos, &c)) { res->status = ST_SEED_INVALID; res->chain = c; return; }
+  if (offs) {
+    c.glossy = true;
+    for (int i = 0; i < n; ++i) { c.off[i][0] = offs[2 * i]; c.off[i][1] = offs[2 * i + 1]; }
+  }
   walk_core(s, p, c, res);
   bool stalled = res->status == ST_STALLED;
   if (res->status != ST_CONVERGED && !stalled) return;
@@ -896,11 +927,12 @@ static bool sample_guided_point(const Scene& s, const Guide& g, int cell, uint64
 }
 
 static int8_t deduce_chain(const Scene& s, const Params& p, int n, int type, const double* coins, double p_transmit,
-                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out);
+                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out,
+                           const double* offs = nullptr);
 
 static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n, int type, int obj1,
                           const V3d& xD, const V3d& nD, uint64_t seed, uint64_t chain, uint64_t trial, double alpha,
-                          int* prim, V3d* pos) {
+                          int* prim, V3d* pos, const double* offs = nullptr) {
   if (n < 1 || n > KMAX || !finite3(xD)) return ST_BAD_INPUT;
   Uniforms U = draw(seed, chain, trial, 0);
   V3d pt;
@@ -914,7 +946,7 @@ static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n
     ok = sample_p0_point(s, p, obj1, xD, nD, U.u[1], U.u[2], U.u[3], &pt);
   }
   if (!ok) return ST_SEED_INVALID;
-  return deduce_chain(s, p, n, type, nullptr, 0.0, xD, pt, prim, pos, nullptr);
+  return deduce_chain(s, p, n, type, nullptr, 0.0, xD, pt, prim, pos, nullptr, offs);
 }
 
 // Eq. (deduction): x_1 = r(x_D, w_D) with w_D towards pt, then x_i = r(x_{i-1},
@@ -925,7 +957,7 @@ static int8_t sample_seed(const Scene& s, const Guide* g, const Params& p, int n
 // p_transmit and reflects otherwise; the decided type is returned in
 // *type_out.  Returns 0 or ST_SEED_INVALID.
 static int8_t deduce_chain(const Scene& s, const Params& p, int n, int type, const double* coins, double p_transmit,
-                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out) {
+                           const V3d& xD, const V3d& pt, int* prim, V3d* pos, int* type_out, const double* offs) {
   const double tmin = p.tmin_rel * p.scale;
   V3d o = xD, d = pt - xD;
   double len = norm(d);
@@ -937,6 +969,8 @@ static int8_t deduce_chain(const Scene& s, const Params& p, int n, int type, con
       // scatter at vertex i-1 with its type (Eq. deduction)
       VGeo gv = make_geo(s, prim[i - 1], pos[i - 1]);
       V3d ns = geo_shading<double>(gv, gv.x);
+      // a glossy vertex scatters about its offset normal (Sec. 5.7)
+      if (offs) ns = offset_normal(kGlossyRef, ns, offs + 2 * (i - 1));
       if ((type >> (i - 1)) & 1) {
         if (gv.mat != MAT_DIELECTRIC) return ST_SEED_INVALID;
         bool entering = dot(d, gv.ng) < 0.0;
@@ -1505,11 +1539,12 @@ static int pick(const double* wts, int count, double total, double u) {
 }
 
 // vMF lobe (Eq. vMF) sampling by inversion of the cosine's distribution:
-// cos theta = 1 + log(u + (1 - u) exp(-2 kappa)) / kappa, phi uniform.
+// 1 - cos theta = -log(u + (1 - u) exp(-2 kappa)) / kappa, phi uniform.
 static V3d sample_vmf(const V3d& mu, double kappa, double u1, double u2) {
-  double ct = 1.0 + std::log(u1 + (1.0 - u1) * std::exp(-2.0 * kappa)) / kappa;
-  ct = std::max(-1.0, std::min(1.0, ct));
-  double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  double v = -std::log(u1 + (1.0 - u1) * std::exp(-2.0 * kappa)) / kappa;
+  v = std::max(0.0, std::min(2.0, v));
+  double ct = 1.0 - v;
+  double st = std::sqrt(std::max(0.0, v * (2.0 - v)));
   V3d b1, b2;
   onb(mu, &b1, &b2);
   double ph = 2.0 * kPi * u2;
@@ -1778,9 +1813,19 @@ static Params to_params(const orc_params* p) {
   return q;
 }
 
+// offsets of glossy chains, [2][K][N] (nullable): vertex i of chain c has
+// (o_s, o_t) = (off[(0 K + i) N + c], off[(1 K + i) N + c])
+static void chain_offsets(const double* off, int N, int c, double* o) {
+  for (int i = 0; i < KMAX; ++i) {
+    o[2 * i] = off[((size_t)0 * KMAX + i) * N + c];
+    o[2 * i + 1] = off[((size_t)1 * KMAX + i) * N + c];
+  }
+}
+
 void orc_sample_seeds(void* sp, const int32_t* gi, const double* gd, const orc_params* pp, int N, const double* xD,
                       const double* nD, const uint8_t* len, const uint8_t* type, const int32_t* obj1, uint64_t seed, uint64_t trial,
-                      double alpha, int32_t* prim_out, double* pos_out, int8_t* status, int nthreads) {
+                      double alpha, int32_t* prim_out, double* pos_out, int8_t* status, int nthreads,
+                      const double* off) {
   const Scene& s = *(Scene*)sp;
   Guide gstore;
   const Guide* g = make_guide_view(gi, gd, &gstore);
@@ -1789,8 +1834,10 @@ void orc_sample_seeds(void* sp, const int32_t* gi, const double* gd, const orc_p
     int prim[KMAX];
     V3d pos[KMAX];
     for (int i = 0; i < KMAX; ++i) { prim[i] = INT32_MIN; pos[i] = V3d(); }
+    double o[2 * KMAX];
+    if (off) chain_offsets(off, N, c, o);
     int8_t st = sample_seed(s, g, p, len[c], type[c], obj1[c], get3d(xD, N, c), get3d(nD, N, c), seed,
-                            (uint64_t)c, trial, alpha, prim, pos);
+                            (uint64_t)c, trial, alpha, prim, pos, off ? o : nullptr);
     status[c] = st;
     for (int i = 0; i < KMAX; ++i) {
       prim_out[(size_t)i * N + c] = st == 0 ? prim[i] : INT32_MIN;
@@ -1803,7 +1850,7 @@ void orc_walk(void* sp, const orc_params* pp, int N, const double* xD, const dou
               const uint8_t* len, const uint8_t* type, const int32_t* seed_prim, const float* seed_pos,
               const int8_t* seed_status, int do_polish, int32_t* prim_out, double* pos_out, int8_t* status,
               int32_t* iters, uint64_t* sol, double* G, double* kappa, double* resid, int8_t* polished,
-              int nthreads) {
+              int nthreads, const double* off) {
   const Scene& s = *(Scene*)sp;
   Params p = to_params(pp);
   parallel_for(N, nthreads, [&](int c) {
@@ -1816,9 +1863,11 @@ void orc_walk(void* sp, const orc_params* pp, int N, const double* xD, const dou
                    seed_pos[((size_t)2 * KMAX + i) * N + c]);
     }
     WalkResult r;
+    double o[2 * KMAX];
+    if (off) chain_offsets(off, N, c, o);
     if (seed_status && seed_status[c] != 0) r.status = ST_SEED_INVALID;
     else walk_chain(s, p, n, type[c], get3d(xD, N, c), get3d(nD, N, c), get3d(xL, N, c), prim, pos,
-                    do_polish != 0, &r);
+                    do_polish != 0, &r, off ? o : nullptr);
     status[c] = r.status;
     iters[c] = r.iters;
     sol[c] = r.status == ST_CONVERGED ? r.sol : 0;
@@ -1896,7 +1945,7 @@ void orc_inv_prob(void* sp, const int32_t* gi, const double* gd, const orc_param
                   const double* nD, const double* xL, const uint8_t* len, const uint8_t* type, const int32_t* obj1,
                   const int32_t* tgt_prim, const double* tgt_pos, const int8_t* tgt_status, int max_trials,
                   int repeats, uint64_t seed, double alpha, int32_t* trials, double* inv_prob, int8_t* truncated,
-                  int nthreads) {
+                  int nthreads, const double* off) {
   const Scene& s = *(Scene*)sp;
   Guide gstore;
   const Guide* g = make_guide_view(gi, gd, &gstore);
@@ -1918,6 +1967,8 @@ void orc_inv_prob(void* sp, const int32_t* gi, const double* gd, const orc_param
             tgt_pos[((size_t)2 * KMAX + i) * N + c]);
       target.v[i] = make_geo(s, tgt_prim[(size_t)i * N + c], x);
     }
+    double o[2 * KMAX];
+    if (off) chain_offsets(off, N, c, o);
     int total = 0;
     for (int r = 0; r < repeats; ++r) {
       int K = max_trials;
@@ -1926,10 +1977,15 @@ void orc_inv_prob(void* sp, const int32_t* gi, const double* gd, const orc_param
         uint64_t trial = 1 + (uint64_t)r * max_trials + (uint64_t)(k - 1);
         int prim[KMAX];
         V3d pos[KMAX];
-        if (sample_seed(s, g, p, n, type[c], obj1[c], xd, nd, seed, (uint64_t)c, trial, alpha, prim, pos) != 0)
+        if (sample_seed(s, g, p, n, type[c], obj1[c], xd, nd, seed, (uint64_t)c, trial, alpha, prim, pos,
+                        off ? o : nullptr) != 0)
           continue;
         Chain start;
         if (!load_chain(s, n, type[c], xd, xl, prim, pos, &start)) continue;
+        if (off) {
+          start.glossy = true;
+          for (int i = 0; i < n; ++i) { start.off[i][0] = o[2 * i]; start.off[i][1] = o[2 * i + 1]; }
+        }
         WalkResult w;
         walk_core(s, p, start, &w);
         bool conv = w.status == ST_CONVERGED || w.status == ST_STALLED;
@@ -2027,6 +2083,24 @@ void orc_adjoint(void* sp, const orc_params* pp, int N, const double* xD, const 
 }
 
 
+// Offset normals of glossy chains (Sec. 5.7) drawn from the GGX
+// (Trowbridge-Reitz) distribution of microfacet normals, D(m) cos theta_m
+// (Walter, Marschner, Li, Torrance, EGSR 2007): tan^2 theta_m = a^2 u / (1 -
+// u), phi = 2 pi v; (o_s, o_t) = sin theta_m (cos phi, sin phi).  Vertex i of
+// chain c uses uniforms 2 (i mod 4) and 2 (i mod 4) + 1 of the Philox block
+// (c, trial, 16 + i / 4).  Layout [2][K][N].
+void orc_sample_offsets(int N, uint64_t seed, uint64_t trial, double roughness, double* off) {
+  for (int c = 0; c < N; ++c)
+    for (int i = 0; i < KMAX; ++i) {
+      Uniforms U = draw(seed, (uint64_t)c, trial, 16 + i / 4);
+      double u = U.u[2 * (i % 4)], v = U.u[2 * (i % 4) + 1];
+      double t2 = roughness * roughness * u / (1.0 - u);
+      double st = std::sqrt(t2 / (1.0 + t2));
+      off[((size_t)0 * KMAX + i) * N + c] = st * std::cos(2.0 * kPi * v);
+      off[((size_t)1 * KMAX + i) * N + c] = st * std::sin(2.0 * kPi * v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The paper's guide: tree, leaf distributions, sampling and trials.
 // Sample records: float [N][16] = x_D (3), x_L (3), w_D (3), w, n, tau, 0 x 4.
@@ -2041,8 +2115,9 @@ void* orc_stree_build(int N, const float* rec, const double* lo, const double* h
     S[j].w = std::isfinite(r[9]) ? r[9] : 0.0;
     S[j].n = (int)r[10];
     S[j].type = (int)r[11];
-    for (int a = 0; a < 6; ++a)
+    for (int a = 0; a < 12; ++a)
       if (!std::isfinite(r[a])) S[j].w = 0.0;
+    if ((float)S[j].n != r[10]) S[j].w = 0.0;
   }
   STree* t = new STree();
   t->sigma_min = sigma_min;

@@ -462,3 +462,190 @@ def manifold_walk_adjoint(scene: Scene, params: mpg_walk_params, ep: Endpoints, 
                                        grad_theta.data_ptr(), ws.h if ws else None, _stream()),
            "manifold_walk_adjoint")
     return grad_xD, grad_xL, grad_theta
+
+
+# ---------------------------------------------------------------------------
+# the paper's guide: 6-D tree, length / type distributions, vMF lobes
+# ---------------------------------------------------------------------------
+
+class mpg_stree_desc(C.Structure):
+    _fields_ = [("lo", F32 * 6), ("hi", F32 * 6), ("eps", F32), ("thr_scale", F32), ("max_depth", I32),
+                ("sigma_min", F32), ("sigma_lone", F32), ("p0n", F32 * 8), ("alpha", F32), ("p_transmit", F32)]
+
+
+def _declare_stree(L):
+    L.mpg_stree_desc_default.argtypes = [C.POINTER(mpg_stree_desc)]
+    L.mpg_stree_create.argtypes = [C.POINTER(mpg_stree_desc), C.POINTER(P)]
+    L.mpg_stree_destroy.argtypes = [P]
+    L.mpg_stree_set_prior.argtypes = [P, P, F32, F32]
+    L.fit_guide_stree.argtypes = [P, P, I32, P]
+    L.mpg_stree_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
+    L.mpg_stree_download.argtypes = [P] * 13
+    L.sample_seeds_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.c_uint64,
+                                     C.c_uint32, P, P, P, C.POINTER(mpg_chains), P, P]
+    L.estimate_inv_prob_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
+                                          C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, P, P, P, P, P]
+    L.make_guide_records.argtypes = [C.POINTER(mpg_endpoints), C.POINTER(mpg_chains), P, P, P, P, P, P]
+    L.mpg_stree_active.argtypes = [P, C.POINTER(mpg_endpoints), P, P]
+    for name in ["mpg_stree_desc_default", "mpg_stree_create", "mpg_stree_set_prior", "fit_guide_stree",
+                 "mpg_stree_stats", "mpg_stree_download", "sample_seeds_stree", "estimate_inv_prob_stree",
+                 "make_guide_records", "mpg_stree_active"]:
+        getattr(L, name).restype = I32
+
+
+def _slib():
+    L = lib()
+    if not getattr(L, "_stree_declared", False):
+        _declare_stree(L)
+        L._stree_declared = True
+    return L
+
+
+class STree:
+    """The paper's guide on the device (see the mpg_stree_* calls)."""
+
+    def __init__(self, lo, hi, eps=0.1, thr_scale=1.0, max_depth=20, sigma_min=1e-3, sigma_lone=0.1, p0n=None,
+                 alpha=0.5, p_transmit=0.5):
+        L = _slib()
+        d = mpg_stree_desc()
+        _check(L.mpg_stree_desc_default(C.byref(d)), "mpg_stree_desc_default")
+        for a in range(6):
+            d.lo[a], d.hi[a] = float(lo[a]), float(hi[a])
+        d.eps, d.thr_scale, d.max_depth = float(eps), float(thr_scale), int(max_depth)
+        d.sigma_min, d.sigma_lone = float(sigma_min), float(sigma_lone)
+        for k in range(8):
+            d.p0n[k] = 1.0 / 8 if p0n is None else float(p0n[k])
+        d.alpha, d.p_transmit = float(alpha), float(p_transmit)
+        h = P()
+        _check(L.mpg_stree_create(C.byref(d), C.byref(h)), "mpg_stree_create")
+        self.h = h.value
+        self.desc = d
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mpg_stree_destroy(self.h)
+            self.h = None
+
+    def set_prior(self, p0n, alpha=0.5, p_transmit=0.5):
+        arr = (F32 * 8)(*[float(v) for v in p0n])
+        _check(_slib().mpg_stree_set_prior(self.h, C.cast(arr, P), float(alpha), float(p_transmit)),
+               "mpg_stree_set_prior")
+
+    def fit(self, records):
+        """records: float32 device tensor [M, 16] (see make_guide_records)."""
+        _check(_slib().fit_guide_stree(self.h, records.data_ptr(), int(records.shape[0]), _stream()),
+               "fit_guide_stree")
+        return self
+
+    def stats(self):
+        v = [I32() for _ in range(4)]
+        _check(_slib().mpg_stree_stats(self.h, *[C.byref(x) for x in v]), "mpg_stree_stats")
+        return dict(zip(("nodes", "leaves", "groups", "lobes"), [x.value for x in v]))
+
+    def download(self):
+        import numpy as np
+        s = self.stats()
+        nn, ng, nl = s["nodes"], s["groups"], s["lobes"]
+        d = dict(axis=np.zeros(nn, np.int32), mid=np.zeros(nn, np.float32), child=np.zeros(nn, np.int32),
+                 W=np.zeros(nn, np.float32), Wn=np.zeros((nn, 8), np.float32), own=np.zeros(nn, np.int32),
+                 leaf_groups=np.zeros((nn, 2), np.int32), grp_key=np.zeros(max(ng, 1), np.int32),
+                 grp_w=np.zeros(max(ng, 1), np.float32), grp_lobes=np.zeros((max(ng, 1), 2), np.int32),
+                 lobe=np.zeros((max(nl, 1), 4), np.float32), lobe_cdf=np.zeros(max(nl, 1), np.float32))
+        keys = ("axis", "mid", "child", "W", "Wn", "own", "leaf_groups", "grp_key", "grp_w", "grp_lobes", "lobe",
+                "lobe_cdf")
+        _check(_slib().mpg_stree_download(self.h, *[d[k].ctypes.data_as(P) for k in keys]), "mpg_stree_download")
+        for k in ("grp_key", "grp_w", "grp_lobes"):
+            d[k] = d[k][:ng]
+        for k in ("lobe", "lobe_cdf"):
+            d[k] = d[k][:nl]
+        return d
+
+
+def sample_seeds_stree(scene: Scene, tree: STree, ep: Endpoints, params: mpg_walk_params, seed=0, trial=0):
+    """Seeds from the paper's guide.  Returns (n, tau, P(n), prim, pos, status)
+    as device tensors; ep.len holds the fixed lengths (0 = sampled)."""
+    torch = _torch()
+    dev = ep.xD.device
+    n = torch.zeros(ep.N, dtype=torch.uint8, device=dev)
+    ty = torch.zeros(ep.N, dtype=torch.uint8, device=dev)
+    pn = torch.zeros(ep.N, dtype=torch.float32, device=dev)
+    prim, pos = empty_chains(ep.N, dev)
+    st = torch.zeros(ep.N, dtype=torch.int8, device=dev)
+    ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
+    _check(_slib().sample_seeds_stree(scene.h, tree.h, C.byref(params), C.byref(ep.c()), int(seed), int(trial),
+                                      n.data_ptr(), ty.data_ptr(), pn.data_ptr(), C.byref(ch), st.data_ptr(),
+                                      _stream()), "sample_seeds_stree")
+    return n, ty, pn, prim, pos, st
+
+
+def estimate_inv_prob_stree(scene: Scene, tree: STree, params: mpg_walk_params, ep: Endpoints, tprim, tpos, tstatus,
+                            max_trials=64, repeats=1, seed=0):
+    """Returns (trials, inv_prob = K / P(n), truncated, P(n)) as device tensors."""
+    torch = _torch()
+    dev = ep.xD.device
+    trials = torch.zeros(ep.N, dtype=torch.int32, device=dev)
+    ip = torch.zeros(ep.N, dtype=torch.float32, device=dev)
+    tr = torch.zeros(ep.N, dtype=torch.uint8, device=dev)
+    pn = torch.zeros(ep.N, dtype=torch.float32, device=dev)
+    ch = mpg_chains(tprim.data_ptr(), tpos.data_ptr())
+    _check(_slib().estimate_inv_prob_stree(scene.h, tree.h, C.byref(params), C.byref(ep.c()), C.byref(ch),
+                                           tstatus.data_ptr(), int(max_trials), int(repeats), int(seed),
+                                           trials.data_ptr(), ip.data_ptr(), tr.data_ptr(), pn.data_ptr(), _stream()),
+           "estimate_inv_prob_stree")
+    return trials, ip, tr, pn
+
+
+def make_guide_records(ep: Endpoints, pos, outs, inv_prob):
+    """Sample records [N, 16] for STree.fit on the device."""
+    torch = _torch()
+    out = torch.empty((ep.N, 16), dtype=torch.float32, device=ep.xD.device)
+    ch = mpg_chains(0, pos.data_ptr())
+    _check(_slib().make_guide_records(C.byref(ep.c()), C.byref(ch), outs["status"].data_ptr(), outs["G"].data_ptr(),
+                                      outs["kappa"].data_ptr(), inv_prob.data_ptr(), out.data_ptr(), _stream()),
+           "make_guide_records")
+    return out
+
+
+def stree_active(tree: STree, ep: Endpoints):
+    """Selective activation flags (uint8 device tensor [N])."""
+    torch = _torch()
+    out = torch.zeros(ep.N, dtype=torch.uint8, device=ep.xD.device)
+    _check(_slib().mpg_stree_active(tree.h, C.byref(ep.c()), out.data_ptr(), _stream()), "mpg_stree_active")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# progressive training schedule (Sec. 5.8)
+# ---------------------------------------------------------------------------
+
+TRAIN, RENDER = 0, 1
+
+
+class mpg_train_plan(C.Structure):
+    _fields_ = [("budget", C.c_double), ("train_fraction", C.c_double), ("base_samples", C.c_int64)]
+
+
+class mpg_train_state(C.Structure):
+    _fields_ = [("phase", I32), ("iteration", I32), ("target", C.c_int64), ("done", C.c_int64), ("refit", I32)]
+
+
+def _tlib():
+    L = lib()
+    if not getattr(L, "_train_declared", False):
+        L.mpg_train_init.argtypes = [C.POINTER(mpg_train_plan), C.POINTER(mpg_train_state)]
+        L.mpg_train_step.argtypes = [C.POINTER(mpg_train_plan), C.POINTER(mpg_train_state), C.c_int64, C.c_double]
+        L.mpg_train_init.restype = I32
+        L.mpg_train_step.restype = I32
+        L._train_declared = True
+    return L
+
+
+def train_init(plan: mpg_train_plan) -> mpg_train_state:
+    st = mpg_train_state()
+    _check(_tlib().mpg_train_init(C.byref(plan), C.byref(st)), "mpg_train_init")
+    return st
+
+
+def train_step(plan: mpg_train_plan, st: mpg_train_state, batch: int, elapsed: float) -> mpg_train_state:
+    _check(_tlib().mpg_train_step(C.byref(plan), C.byref(st), int(batch), float(elapsed)), "mpg_train_step")
+    return st

@@ -14,9 +14,9 @@ LIB = os.path.join(HERE, "libmpg.so")
 SOURCES = ["mpg_adjoint_plain_a.hip", "mpg_adjoint_plain_b.hip", "mpg_adjoint_plain_c.hip", "mpg_count_a.hip",
            "mpg_count_b.hip", "mpg_count_c.hip", "mpg_persistent.hip", "mpg_lib.hip", "mpg_trials.hip",
            "mpg_adjoint.hip", "mpg_guide.hip", "mpg_adjoint_plain.hip", "mpg_count.hip", "mpg_params.hip",
-           "mpg_noalloc.hip", "mpg_scene.cpp"]
+           "mpg_noalloc.hip", "mpg_stree.hip", "mpg_stree_host.cpp", "mpg_train.cpp", "mpg_scene.cpp"]
 HEADERS = ["mpg_device.h", "mpg_internal.h", "mpg_walk.h", "mpg_scene.h", "mpg_adjoint.h", "mpg_adjoint_plain.h",
-           "mpg_count.h"]
+           "mpg_count.h", "mpg_stree_host.h"]
 DEPS = SOURCES + HEADERS
 
 HIPCC_FLAGS = [
@@ -31,15 +31,28 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+OBJDIR = os.path.join(HERE, "_build")
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every unit and links libmpg.so.  incremental=True keeps the
+    objects in _build/ and recompiles only units older than their source or
+    any header (a development convenience; the default builds from scratch)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I", os.path.join(os.path.dirname(HERE), "include")]
     jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    headers = [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(os.path.dirname(HERE), "include", "mpg.h")]
+    newest_header = max(os.path.getmtime(h) for h in headers if os.path.exists(h))
     with tempfile.TemporaryDirectory(prefix="mpg_build_") as tmpdir:
-        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        objdir = OBJDIR if incremental else tmpdir
+        os.makedirs(objdir, exist_ok=True)
+        objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
 
         def compile_one(k):
             src = os.path.join(CSRC, SOURCES[k])
+            if incremental and os.path.exists(objs[k]) and \
+                    os.path.getmtime(objs[k]) > max(os.path.getmtime(src), newest_header):
+                return
             lang = ["-x", "hip"] if src.endswith(".hip") else []
             cmd = [hipcc, *HIPCC_FLAGS, *inc, *lang, "-c", src, "-o", objs[k]]
             if verbose:
@@ -65,5 +78,5 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

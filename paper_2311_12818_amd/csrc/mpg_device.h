@@ -1143,6 +1143,10 @@ __device__ __forceinline__ bool guided_point(const DevScene& S, const DevGuide& 
   return false;
 }
 
+template <int N, bool COINS, class STK>
+__device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, int type, const float* coins,
+                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out);
+
 // One seed chain of length N.  Returns 0 or ST_SEED_INVALID.
 template <int N, class STK>
 __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G, const WalkParams& P, int type, int obj1, f3 xD,
@@ -1157,6 +1161,18 @@ __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G,
   if (guided) ok = guided_point(S, *G, cell, seed, chain, trial, U, stk, pt);
   if (!ok) ok = p0_point(S, P, obj1, xD, nD, U.u[1], U.u[2], U.u[3], pt);
   if (!ok) return ST_SEED_INVALID;
+  return deduce<N, false>(S, P, type, nullptr, 0.0f, xD, pt, prim, pos, stk, nullptr);
+}
+
+// Eq. (deduction): x_1 = r(x_D, w_D) with w_D towards pt, then x_i =
+// r(x_{i-1}, s_tau(x_{i-1}, ...)).  COINS = false: the given type.  COINS =
+// true: the type of each vertex is decided when the ray reaches it, as a path
+// tracer would (Sec. 5.4): a mirror reflects, a dielectric transmits when its
+// coin (coins[i]) is below p_transmit; the decided type goes to *type_out.
+// Returns 0 or ST_SEED_INVALID.
+template <int N, bool COINS, class STK>
+__device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, int type, const float* coins,
+                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out) {
   f3 d = pt - xD;
   float l2 = dot(d, d);
   if (!(l2 > 0.0f)) return ST_SEED_INVALID;
@@ -1189,11 +1205,16 @@ __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G,
     if (!trace(S, o, d, excl, P.tmin, h, stk) || h.prim == PRIM_NONE) return ST_SEED_INVALID;
     prim[i] = h.prim;
     pos[i] = fmav(d, h.t, o);
+    if (COINS) {
+      bool transmit = S.obj_info[prim_obj(S, h.prim)].x == MAT_DIELECTRIC && coins[i] < p_transmit;
+      type = transmit ? (type | (1 << i)) : (type & ~(1 << i));
+    }
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     if (((type >> i) & 1) && S.obj_info[prim_obj(S, prim[i])].x != MAT_DIELECTRIC) return ST_SEED_INVALID;
   }
+  if (COINS) *type_out = type;
   return 0;
 }
 

@@ -56,7 +56,7 @@ def test_ctypes_structs_match_the_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = [M.mpg_heightfield, M.mpg_scene_desc, M.mpg_endpoints, M.mpg_chains, M.mpg_walk_out,
-               M.mpg_walk_params, M.mpg_guide_desc]
+               M.mpg_walk_params, M.mpg_guide_desc, M.mpg_stree_desc]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mpg.h"', "int main(void) {"]
     expect = []
     for S in structs:
