@@ -162,6 +162,10 @@ typedef struct {
   const uint8_t* d_len;   /* [N] 1..8 */
   const uint8_t* d_type;  /* [N] */
   const int32_t* d_obj1;  /* [N] */
+  const float* d_offset;  /* [2][K][N] offset normals (o_s, o_t) of glossy chains (Sec. 5.7), or NULL for
+                             specular chains: vertex i of chain c is specular about m = o_s s + o_t t +
+                             sqrt(1 - |o|^2) n_s, with s the world x axis projected on the tangent plane
+                             and t = n_s x s (see sample_offsets) */
 } mpg_endpoints;
 
 /* Chains: primitive id and position of each specular vertex. */
@@ -266,6 +270,17 @@ mpg_status mpg_guide_download(const mpg_guide* g, int32_t* valid, float* pi, flo
 mpg_status sample_seeds(const mpg_scene* scene, const mpg_guide* guide, const mpg_walk_params* params,
                         const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, float alpha,
                         mpg_chains* out, int8_t* d_status, mpg_workspace* ws, void* hip_stream);
+
+/* Offset normals of glossy chains (Sec. 5.7), sampled before the walk: per
+ * chain and vertex, (o_s, o_t) = sin theta_m (cos phi, sin phi) of a
+ * microfacet normal drawn from the GGX distribution D(m) cos theta_m with
+ * the given roughness (tan^2 theta_m = roughness^2 u / (1 - u), phi = 2 pi
+ * v; Philox block (chain, trial, 16 + i / 4), uniforms 2 (i mod 4) and
+ * 2 (i mod 4) + 1 for vertex i).  d_offset is [2][K][N]; pass it as
+ * mpg_endpoints.d_offset to seed, walk and estimate glossy chains.  Errors:
+ * N < 0, NULL output, roughness outside [0, 1]. */
+mpg_status sample_offsets(int32_t N, uint64_t philox_seed, uint32_t trial, float roughness, float* d_offset,
+                          void* hip_stream);
 
 /* Manifold walks (Sec. 3): Newton's method on the generalized half-vector
  * constraints with a block-tridiagonal Jacobian, reprojection by ray casting,

@@ -61,7 +61,7 @@ def _declare(L):
     L.orc_solution_id.argtypes = [C.c_int, C.c_int, P]
     L.orc_raycast.argtypes = [P, C.c_int, P, P, P, D, C.c_int, P, P, C.c_int]
     L.orc_constraint.restype = C.c_int
-    L.orc_constraint.argtypes = [P, C.c_int, C.c_int, P, P, P, P, P, P, P]
+    L.orc_constraint.argtypes = [P, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
     L.orc_offset_positions.restype = C.c_int
     L.orc_offset_positions.argtypes = [P, C.c_int, P, P, P, P]
     L.orc_sample_seeds.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, U64, U64, D, P, P,
@@ -71,7 +71,7 @@ def _declare(L):
                            P, P, P, P, C.c_int, P]
     L.orc_inv_prob.argtypes = [P, P, P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, C.c_int,
                                C.c_int, U64, D, P, P, P, C.c_int, P]
-    L.orc_validate.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, C.c_int]
+    L.orc_validate.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, C.c_int, P]
     L.orc_scene_set_theta.restype = C.c_int
     L.orc_scene_set_theta.argtypes = [P, C.c_int, P]
     L.orc_adjoint.argtypes = [P, C.POINTER(orc_params), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
@@ -157,13 +157,14 @@ def raycast(osc: Scene, o, d, exclude=None, tmin=0.0, brute=False, nthreads=0):
     return prim, t
 
 
-def constraint(osc: Scene, n, type_, xD, xL, prims, pos):
+def constraint(osc: Scene, n, type_, xD, xL, prims, pos, offsets=None):
     """Residual C (2n) and dense Jacobian J (2n x 2n) w.r.t. local offsets; frames (n, 2, 3)."""
     Cv = np.zeros(2 * n)
     J = np.zeros((2 * n, 2 * n))
     fr = np.zeros((n, 2, 3))
     rc = lib().orc_constraint(osc.h, n, type_, _p(_c(xD, np.float64)), _p(_c(xL, np.float64)),
-                              _p(_c(prims, np.int32)), _p(_c(pos, np.float64).reshape(-1)), _p(Cv), _p(J), _p(fr))
+                              _p(_c(prims, np.int32)), _p(_c(pos, np.float64).reshape(-1)), _p(Cv), _p(J), _p(fr),
+                              _p(None if offsets is None else _c(offsets, np.float64).reshape(-1)))
     if rc != 0:
         raise ValueError("invalid chain")
     return Cv, J, fr
@@ -256,7 +257,7 @@ def walk(osc: Scene, ep, seed_prim, seed_pos, seed_status=None, polish=True, prm
     return out
 
 
-def validate(osc: Scene, ep, prim, pos, prm=None, nthreads=0):
+def validate(osc: Scene, ep, prim, pos, prm=None, nthreads=0, offsets=None):
     """FP64 admissibility of given chains (e.g. the GPU's converged chains):
     polish from the given vertices, then side and visibility tests.  Returns
     a dict of per-chain arrays: ok, residual, moved, side, visible,
@@ -268,7 +269,7 @@ def validate(osc: Scene, ep, prim, pos, prm=None, nthreads=0):
     lib().orc_validate(osc.h, C.byref(prm), N, _p(_c(ep.xD, np.float64)), _p(_c(ep.xL, np.float64)),
                        _p(_c(ep.length, np.uint8)), _p(_c(ep.types, np.uint8)), _p(_c(prim, np.int32)),
                        _p(_c(pos, np.float64)), _p(out["ok"]), _p(out["residual"]), _p(out["moved"]),
-                       _p(out["side"]), _p(out["visible"]), _p(out["same_prims"]), nthreads)
+                       _p(out["side"]), _p(out["visible"]), _p(out["same_prims"]), nthreads, _p(_off(offsets)))
     return out
 
 

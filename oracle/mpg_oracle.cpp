@@ -1763,12 +1763,16 @@ void orc_raycast(void* sp, int n, const double* o, const double* d, const int32_
 
 // Residual and dense Jacobian of one chain at given primitives / positions.
 int orc_constraint(void* sp, int n, int type, const double* xD, const double* xL, const int32_t* prim,
-                   const double* pos, double* C, double* J, double* frames) {
+                   const double* pos, double* C, double* J, double* frames, const double* off) {
   const Scene& s = *(Scene*)sp;
   Chain c;
   V3d p[KMAX];
   for (int i = 0; i < n; ++i) p[i] = V3d(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
   if (!load_chain(s, n, type, V3d(xD[0], xD[1], xD[2]), V3d(xL[0], xL[1], xL[2]), prim, p, &c)) return -1;
+  if (off) {  // glossy offsets (o_s, o_t) per vertex
+    c.glossy = true;
+    for (int i = 0; i < n; ++i) { c.off[i][0] = off[2 * i]; c.off[i][1] = off[2 * i + 1]; }
+  }
   jacobian(c, V3d(), V3d(), C, J, nullptr);
   if (frames)
     for (int i = 0; i < n; ++i) {
@@ -1894,7 +1898,8 @@ void orc_walk(void* sp, const orc_params* pp, int N, const double* xD, const dou
 // whether the polish kept every primitive id.
 void orc_validate(void* sp, const orc_params* pp, int N, const double* xD, const double* xL, const uint8_t* len,
                   const uint8_t* type, const int32_t* prim_in, const double* pos_in, int8_t* ok, double* resid,
-                  double* moved, int8_t* side, int8_t* visible, int8_t* same_prims, int nthreads) {
+                  double* moved, int8_t* side, int8_t* visible, int8_t* same_prims, int nthreads,
+                  const double* off) {
   const Scene& s = *(Scene*)sp;
   Params p = to_params(pp);
   parallel_for(N, nthreads, [&](int c) {
@@ -1920,6 +1925,12 @@ void orc_validate(void* sp, const orc_params* pp, int N, const double* xD, const
     }
     WalkResult r;
     if (!load_chain(s, n, type[c], get3d(xD, N, c), get3d(xL, N, c), prim, pos, &r.chain)) return;
+    if (off) {
+      double o[2 * KMAX];
+      chain_offsets(off, N, c, o);
+      r.chain.glossy = true;
+      for (int i = 0; i < n; ++i) { r.chain.off[i][0] = o[2 * i]; r.chain.off[i][1] = o[2 * i + 1]; }
+    }
     ok[c] = 1;
     polish(s, p, &r);
     resid[c] = r.residual;

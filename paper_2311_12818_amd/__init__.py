@@ -53,7 +53,8 @@ class mpg_scene_desc(C.Structure):
 
 
 class mpg_endpoints(C.Structure):
-    _fields_ = [("N", I32), ("d_xD", P), ("d_nD", P), ("d_xL", P), ("d_len", P), ("d_type", P), ("d_obj1", P)]
+    _fields_ = [("N", I32), ("d_xD", P), ("d_nD", P), ("d_xL", P), ("d_len", P), ("d_type", P), ("d_obj1", P),
+                ("d_offset", P)]
 
 
 class mpg_chains(C.Structure):
@@ -297,6 +298,7 @@ class Endpoints:
         self.len = _dev(ep.length, torch.uint8, device)
         self.type = _dev(ep.types, torch.uint8, device)
         self.obj1 = _dev(ep.obj1, torch.int32, device)
+        self.off = None   # glossy offset normals [2][K][N] (float32 device tensor), see sample_offsets
 
     @classmethod
     def from_tensors(cls, xD, nD, xL, length, types, obj1):
@@ -306,6 +308,7 @@ class Endpoints:
         self.N = int(length.shape[0])
         self.xD, self.nD, self.xL = xD.contiguous(), nD.contiguous(), xL.contiguous()
         self.len, self.type, self.obj1 = length.contiguous(), types.contiguous(), obj1.contiguous()
+        self.off = None
         for t, dt in ((self.xD, "float32"), (self.nD, "float32"), (self.xL, "float32"), (self.len, "uint8"),
                       (self.type, "uint8"), (self.obj1, "int32")):
             if str(t.dtype) != "torch." + dt or not t.is_cuda:
@@ -314,7 +317,8 @@ class Endpoints:
 
     def c(self) -> mpg_endpoints:
         return mpg_endpoints(self.N, self.xD.data_ptr(), self.nD.data_ptr(), self.xL.data_ptr(),
-                             self.len.data_ptr(), self.type.data_ptr(), self.obj1.data_ptr())
+                             self.len.data_ptr(), self.type.data_ptr(), self.obj1.data_ptr(),
+                             self.off.data_ptr() if self.off is not None else None)
 
 
 def empty_chains(N, device="cuda"):
@@ -380,6 +384,18 @@ def manifold_walk_batch_noalloc(scene: Scene, params: mpg_walk_params, ep: Endpo
                                              _ptr(seed_status), C.byref(oc), C.byref(_wout(outs)), _stream()),
            "manifold_walk_batch_noalloc")
     return out_prim, out_pos, outs
+
+
+def sample_offsets(N, seed=0, trial=0, roughness=0.1, device="cuda"):
+    """GGX offset normals of glossy chains: float32 device tensor [2][K][N]."""
+    torch = _torch()
+    out = torch.zeros((2, KMAX, N), dtype=torch.float32, device=device)
+    L = lib()
+    L.sample_offsets.argtypes = [I32, C.c_uint64, C.c_uint32, F32, P, P]
+    L.sample_offsets.restype = I32
+    _check(L.sample_offsets(int(N), int(seed), int(trial), float(roughness), out.data_ptr(), _stream()),
+           "sample_offsets")
+    return out
 
 
 def _wout(outs):

@@ -584,24 +584,41 @@ struct VJ {
   T cmin;            // min(|w_i.n_s|, |w_o.n_s|): grazing measure
 };
 
+//
+// Glossy vertices (Sec. 5.7) carry an offset normal m = o_s s + o_t t +
+// sqrt(1 - |o|^2) n_s and are specular about it: C = (sg h.s - o_s,
+// sg h.t - o_t) with sg = sign(h.n_s), the frame (s, t) built from the world
+// x axis instead of e1 so that it turns smoothly across triangles; the
+// blocks scale by sg (the offsets are constants).
+template <typename T>
+__device__ __forceinline__ vec3<T> glossy_ref() { return vec3<T>{(T)1, (T)0, (T)0}; }
+
 template <typename T, bool JAC>
 __device__ __forceinline__ void vertex_cj(const Geo<T>& g, vec3<T> xp, vec3<T> xn, T ea, T eb, vec3<T> pe1,
-                                          vec3<T> pe2, vec3<T> ne1, vec3<T> ne2, VJ<T>& o) {
+                                          vec3<T> pe2, vec3<T> ne1, vec3<T> ne2, VJ<T>& o, bool glossy = false,
+                                          T os = 0, T ot = 0) {
   vec3<T> di = xp - g.x, dq = xn - g.x;
   T ili = rsq(dot(di, di)), ilo = rsq(dot(dq, dq));
   vec3<T> wi = di * ili, wo = dq * ilo;
   vec3<T> h = wi * ea + wo * eb;
   T ilh = rsq(dot(h, h));
   vec3<T> hh = h * ilh;
-  vec3<T> st = g.e1 - g.ns * dot(g.e1, g.ns);
+  const vec3<T> ref = glossy ? glossy_ref<T>() : g.e1;
+  vec3<T> st = ref - g.ns * dot(ref, g.ns);
   T ils = rsq(dot(st, st));
   vec3<T> s = st * ils;
   vec3<T> t = cross(g.ns, s);
-  o.C0 = dot(hh, s);
-  o.C1 = dot(hh, t);
+  const T hs = dot(hh, s), ht = dot(hh, t);
+  o.C0 = hs;
+  o.C1 = ht;
+  const T sg = glossy && dot(hh, g.ns) < (T)0 ? (T)-1 : (T)1;
+  if (glossy) {
+    o.C0 = sg * hs - os;
+    o.C1 = sg * ht - ot;
+  }
   if (!JAC) return;
   o.cmin = fmin(fabs(dot(wi, g.ns)), fabs(dot(wo, g.ns)));
-  vec3<T> Qs = (s - hh * o.C0) * ilh, Qt = (t - hh * o.C1) * ilh;
+  vec3<T> Qs = (s - hh * hs) * ilh, Qt = (t - hh * ht) * ilh;
   vec3<T> gsi = (Qs - wi * dot(wi, Qs)) * (ea * ili);
   vec3<T> gti = (Qt - wi * dot(wi, Qt)) * (ea * ili);
   vec3<T> gso = (Qs - wo * dot(wo, Qs)) * (eb * ilo);
@@ -611,19 +628,48 @@ __device__ __forceinline__ void vertex_cj(const Geo<T>& g, vec3<T> xp, vec3<T> x
   o.L[0] = dot(gsi, pe1); o.L[1] = dot(gsi, pe2); o.L[2] = dot(gti, pe1); o.L[3] = dot(gti, pe2);
   o.U[0] = dot(gso, ne1); o.U[1] = dot(gso, ne2); o.U[2] = dot(gto, ne1); o.U[3] = dot(gto, ne2);
   vec3<T> gs = gsi + gso, gt = gti + gto;
-  T e1n = dot(g.e1, g.ns);
+  T e1n = dot(ref, g.ns);
   vec3<T> sxh = cross(s, hh), hxn = cross(hh, g.ns);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     vec3<T> ek = k == 0 ? g.e1 : g.e2;
     vec3<T> dn = k == 0 ? g.dns_a : g.dns_b;
-    vec3<T> dst = g.ns * (-dot(g.e1, dn)) - dn * e1n;
+    vec3<T> dst = g.ns * (-dot(ref, dn)) - dn * e1n;
     vec3<T> ds = (dst - s * dot(s, dst)) * ils;
     // h.dt with dt = dn x s + n x ds
     T hdt = dot(dn, sxh) + dot(ds, hxn);
     o.D[k] = -dot(gs, ek) + dot(hh, ds);
     o.D[2 + k] = -dot(gt, ek) + hdt;
   }
+  if (glossy) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { o.L[k] *= sg; o.D[k] *= sg; o.U[k] *= sg; }
+    o.gso = o.gso * sg;
+    o.gto = o.gto * sg;
+  }
+}
+
+// Offset normals of a glossy chain: [2][K][N] device array (null: specular),
+// chain c; (o_s, o_t) of vertex i.
+struct Offs {
+  const float* p;
+  size_t NN;
+  int c;
+  __device__ __forceinline__ float s(int i) const { return p[(0 * KMAX + i) * NN + c]; }
+  __device__ __forceinline__ float t(int i) const { return p[(1 * KMAX + i) * NN + c]; }
+};
+__device__ __forceinline__ Offs no_offs() { return Offs{nullptr, 0, 0}; }
+
+// The offset normal of a glossy vertex from its shading normal.
+template <typename T>
+__device__ __forceinline__ vec3<T> offset_normal(vec3<T> ns, T os, T ot) {
+  const vec3<T> ref = glossy_ref<T>();
+  vec3<T> st = ref - ns * dot(ref, ns);
+  vec3<T> s = st * rsq(dot(st, st));
+  vec3<T> t = cross(ns, s);
+  T c = sqrt(fmax((T)0, (T)1 - os * os - ot * ot));
+  vec3<T> m = s * os + t * ot + ns * c;
+  return m * rsq(dot(m, m));
 }
 
 template <typename T>
@@ -667,7 +713,7 @@ struct Sweep {
 template <typename T, int N, bool JAC, class STK, bool BACK = true>
 __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL, int type, const int* prim,
                                       const vec3<T>* x, Sweep<T, N>& W, STK& stk,
-                                      const ThetaDir* td = nullptr) {
+                                      const ThetaDir* td = nullptr, Offs off = Offs{nullptr, 0, 0}) {
   T g[N][2];
   W.c2 = 0;
   W.cinf = 0;
@@ -689,8 +735,12 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
     if (!JAC) stk.vc();
     else if (sizeof(T) == 4) stk.vj();
     else stk.vj64();
-    vertex_cj<T, JAC>(gc, xp, xn, ea, eb, pe1, pe2, N > 1 && i < N - 1 ? gn.e1 : gc.e1,
-                      N > 1 && i < N - 1 ? gn.e2 : gc.e2, v);
+    if (off.p)
+      vertex_cj<T, JAC>(gc, xp, xn, ea, eb, pe1, pe2, N > 1 && i < N - 1 ? gn.e1 : gc.e1,
+                        N > 1 && i < N - 1 ? gn.e2 : gc.e2, v, true, (T)off.s(i), (T)off.t(i));
+    else
+      vertex_cj<T, JAC>(gc, xp, xn, ea, eb, pe1, pe2, N > 1 && i < N - 1 ? gn.e1 : gc.e1,
+                        N > 1 && i < N - 1 ? gn.e2 : gc.e2, v);
     W.Cv[i][0] = v.C0;
     W.Cv[i][1] = v.C1;
     W.c2 += v.C0 * v.C0 + v.C1 * v.C1;
@@ -813,10 +863,10 @@ __device__ __forceinline__ void walk_begin(const DevScene& S, WalkState<N>& w) {
 // the lane-refill kernel interleaves it with taking new chains.
 template <int N, class STK>
 __device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type,
-                                         WalkState<N>& w, STK& stk) {
+                                         WalkState<N>& w, STK& stk, Offs off = Offs{nullptr, 0, 0}) {
   if (w.need_jac) {
     Sweep<float, N> W;
-    sweep<float, N, true>(S, xD, xL, type, w.prim, w.x, W, stk);
+    sweep<float, N, true>(S, xD, xL, type, w.prim, w.x, W, stk, nullptr, off);
     if (W.singular) return ST_SINGULAR;
     w.c2 = W.c2;
     w.step2 = 0.0f;
@@ -838,7 +888,7 @@ __device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P,
     return -1;
   }
   Sweep<float, N> Wc;
-  sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc, stk);
+  sweep<float, N, false>(S, xD, xL, type, pn, xn, Wc, stk, nullptr, off);
   const bool done = small && Wc.cinf <= P.tol_residual;
   if (done || Wc.c2 < w.c2) {
 #pragma unroll
@@ -858,13 +908,13 @@ __device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P,
 
 template <int N, class STK>
 __device__ __forceinline__ int walk_core(const DevScene& S, const WalkParams& P, f3 xD, f3 xL, int type, int* prim, f3* x,
-                         int& iters, STK& stk) {
+                         int& iters, STK& stk, Offs off = Offs{nullptr, 0, 0}) {
   WalkState<N> w;
 #pragma unroll
   for (int i = 0; i < N; ++i) { w.prim[i] = prim[i]; w.x[i] = x[i]; }
   walk_begin<N>(S, w);
   int st;
-  while ((st = walk_step<N>(S, P, xD, xL, type, w, stk)) < 0) {
+  while ((st = walk_step<N>(S, P, xD, xL, type, w, stk, off)) < 0) {
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) { prim[i] = w.prim[i]; x[i] = w.x[i]; }
@@ -890,9 +940,9 @@ __device__ __forceinline__ float fresnel(float cos_i, float eta_i, float eta_t) 
 // On success xd holds the FP64 vertices and W their FP64 Jacobian sweep.
 template <int N, class STK>
 __device__ __forceinline__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int type, const int* prim, d3* xd,
-                           Sweep<double, N>& W, float& resid, STK& stk) {
+                           Sweep<double, N>& W, float& resid, STK& stk, Offs off = Offs{nullptr, 0, 0}) {
   for (int k = 0; k < 2; ++k) {
-    sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk);
+    sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk, nullptr, off);
     if (W.cinf < 1e-12 || W.singular) break;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -905,7 +955,7 @@ __device__ __forceinline__ bool fp64_check(const DevScene& S, d3 xD, d3 xL, int 
       xd[i] = nx;
     }
   }
-  sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk);
+  sweep<double, N, true>(S, xD, xL, type, prim, xd, W, stk, nullptr, off);
   resid = (float)W.cinf;
   return W.cinf < 1e-6 && !W.singular;
 }
@@ -942,7 +992,8 @@ __device__ __forceinline__ double fresnel_t(double cos_i, double eta_i, double e
 
 template <typename T, int N, class STK>
 __device__ __forceinline__ void finish_with(const DevScene& S, const WalkParams& P, vec3<T> xD, vec3<T> nD, vec3<T> xL, int type,
-                            const int* prim, const vec3<T>* x, const Sweep<T, N>& W, STK& stk, WalkOut& R) {
+                            const int* prim, const vec3<T>* x, const Sweep<T, N>& W, STK& stk, WalkOut& R,
+                            Offs off = Offs{nullptr, 0, 0}) {
   T kappa = 1;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -955,7 +1006,9 @@ __device__ __forceinline__ void finish_with(const DevScene& S, const WalkParams&
     if (g.mat != MAT_MIRROR) {
       vec3<T> wi = normalize(xp - x[i]);
       bool outside = a > (T)0;
-      T F = fresnel_t(dot(wi, g.ns), outside ? (T)1 : g.ior, outside ? g.ior : (T)1);
+      // a glossy vertex scatters at its offset normal
+      vec3<T> nm = off.p ? offset_normal<T>(g.ns, (T)off.s(i), (T)off.t(i)) : g.ns;
+      T F = fresnel_t(dot(wi, nm), outside ? (T)1 : g.ior, outside ? g.ior : (T)1);
       kappa *= Tr ? (T)1 - F : F;
     }
   }
@@ -1003,30 +1056,31 @@ __device__ __forceinline__ void finish_with(const DevScene& S, const WalkParams&
 // for the FP64 pass; the others are finished in FP32.
 template <int N, class STK>
 __device__ __forceinline__ void finish(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
-                       const f3* x, STK& stk, WalkOut& R) {
+                       const f3* x, STK& stk, WalkOut& R, Offs off = Offs{nullptr, 0, 0}) {
   Sweep<float, N> W;
-  sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk);
+  sweep<float, N, true>(S, xD, xL, type, prim, x, W, stk, nullptr, off);
   R.resid = W.cinf;
   if (W.singular || !(W.cond <= P.fp64_cond) || !(W.cmin >= P.graze_cos)) { R.status = ST_NEEDS_FP64; return; }
-  finish_with<float, N, STK>(S, P, xD, nD, xL, type, prim, x, W, stk, R);
+  finish_with<float, N, STK>(S, P, xD, nD, xL, type, prim, x, W, stk, R, off);
 }
 
 // FP64 pass for one flagged chain: FP64 residual check and polish, then the
 // side / visibility tests, kappa and G in FP64.
 template <int N, class STK>
 __device__ __forceinline__ void finish_fp64(const DevScene& S, const WalkParams& P, f3 xD, f3 nD, f3 xL, int type, const int* prim,
-                            f3* x, STK& stk, WalkOut& R) {
+                            f3* x, STK& stk, WalkOut& R, Offs off = Offs{nullptr, 0, 0}) {
   d3 xd[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) xd[i] = cvt<double>(x[i]);
   Sweep<double, N> W;
   float r64;
-  bool ok = fp64_check<N>(S, cvt<double>(xD), cvt<double>(xL), type, prim, xd, W, r64, stk);
+  bool ok = fp64_check<N>(S, cvt<double>(xD), cvt<double>(xL), type, prim, xd, W, r64, stk, off);
   R.resid = r64;
   if (!ok) { R.status = ST_FP64_REJECT; return; }
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = cvt<float>(xd[i]);
-  finish_with<double, N, STK>(S, P, cvt<double>(xD), cvt<double>(nD), cvt<double>(xL), type, prim, xd, W, stk, R);
+  finish_with<double, N, STK>(S, P, cvt<double>(xD), cvt<double>(nD), cvt<double>(xL), type, prim, xd, W, stk, R,
+                              off);
 }
 
 // ---------------------------------------------------------------------------
@@ -1145,13 +1199,14 @@ __device__ __forceinline__ bool guided_point(const DevScene& S, const DevGuide& 
 
 template <int N, bool COINS, class STK>
 __device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, int type, const float* coins,
-                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out);
+                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out,
+                                      Offs off = Offs{nullptr, 0, 0});
 
 // One seed chain of length N.  Returns 0 or ST_SEED_INVALID.
 template <int N, class STK>
 __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G, const WalkParams& P, int type, int obj1, f3 xD,
                            f3 nD, uint64_t seed, uint64_t chain, uint64_t trial, float alpha, int* prim, f3* pos,
-                           STK& stk) {
+                           STK& stk, Offs off = Offs{nullptr, 0, 0}) {
   U8 U = philox_uniforms(seed, chain, trial, 0);
   f3 pt;
   bool ok = false;
@@ -1161,7 +1216,7 @@ __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G,
   if (guided) ok = guided_point(S, *G, cell, seed, chain, trial, U, stk, pt);
   if (!ok) ok = p0_point(S, P, obj1, xD, nD, U.u[1], U.u[2], U.u[3], pt);
   if (!ok) return ST_SEED_INVALID;
-  return deduce<N, false>(S, P, type, nullptr, 0.0f, xD, pt, prim, pos, stk, nullptr);
+  return deduce<N, false>(S, P, type, nullptr, 0.0f, xD, pt, prim, pos, stk, nullptr, off);
 }
 
 // Eq. (deduction): x_1 = r(x_D, w_D) with w_D towards pt, then x_i =
@@ -1172,7 +1227,8 @@ __device__ __forceinline__ int sample_seed(const DevScene& S, const DevGuide* G,
 // Returns 0 or ST_SEED_INVALID.
 template <int N, bool COINS, class STK>
 __device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, int type, const float* coins,
-                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out) {
+                                      float p_transmit, f3 xD, f3 pt, int* prim, f3* pos, STK& stk, int* type_out,
+                                      Offs off) {
   f3 d = pt - xD;
   float l2 = dot(d, d);
   if (!(l2 > 0.0f)) return ST_SEED_INVALID;
@@ -1185,6 +1241,8 @@ __device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, in
       int pp = prim[i > 0 ? i - 1 : 0];
       f3 xp = pos[i > 0 ? i - 1 : 0];
       Geo<float> g = load_geo<float, false>(S, pp, xp);
+      // a glossy vertex scatters about its offset normal (Sec. 5.7)
+      if (off.p) g.ns = offset_normal<float>(g.ns, off.s(i > 0 ? i - 1 : 0), off.t(i > 0 ? i - 1 : 0));
       if ((type >> (i - 1)) & 1) {
         if (g.mat != MAT_DIELECTRIC) return ST_SEED_INVALID;
         bool entering = dot(d, g.ng) < 0.0f;

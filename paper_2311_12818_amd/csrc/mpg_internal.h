@@ -128,8 +128,10 @@ struct EpView {
   const uint8_t* len;
   const uint8_t* type;
   const int32_t* obj1;
+  const float* off;  // glossy offset normals [2][K][N] or null
   int N;
 };
+__device__ __forceinline__ Offs chain_offs(const EpView& E, int c) { return Offs{E.off, (size_t)E.N, c}; }
 __device__ __forceinline__ f3 ld_pt(const float* a, int N, int i) { return {a[i], a[N + i], a[2 * (size_t)N + i]}; }
 __device__ __forceinline__ bool finite3(f3 v) { return isfinite(v.x) && isfinite(v.y) && isfinite(v.z); }
 

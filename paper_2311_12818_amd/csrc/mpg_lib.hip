@@ -447,6 +447,7 @@ mpg_status check_endpoints(const mpg_endpoints* e, EpView* v) {
   if (e->N > 0 && (!e->d_xD || !e->d_nD || !e->d_xL || !e->d_len || !e->d_type || !e->d_obj1))
     return fail(MPG_ERR_INVALID_ARG, "NULL endpoint array");
   v->xD = e->d_xD; v->nD = e->d_nD; v->xL = e->d_xL; v->len = e->d_len; v->type = e->d_type; v->obj1 = e->d_obj1;
+  v->off = e->d_offset;
   v->N = e->N;
   return MPG_OK;
 }

@@ -283,7 +283,7 @@ k_walk_refill(DevScene S, WalkParams P, EpView E, WalkIO io, int* ctr, const int
       continue;
     }
     if (c >= 0) {
-      const int st = walk_step<N>(S, P, xD, xL, type, w, stk);
+      const int st = walk_step<N>(S, P, xD, xL, type, w, stk, chain_offs(E, c));
       if (st >= 0) {
         store_walk<N>(E, io, c, st, w.it, true, w.prim, w.x);
         c = -1;

@@ -39,10 +39,11 @@ __device__ __forceinline__ void inv_one(const DevScene& S, const DevGuide* G, co
       uint64_t trial = 1 + (uint64_t)r * io.max_trials + (uint64_t)(k - 1);
       int prim[N];
       f3 x[N];
-      if (sample_seed<N>(S, G, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, prim, x, stk) != 0)
+      if (sample_seed<N>(S, G, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, prim, x, stk,
+                         chain_offs(E, c)) != 0)
         continue;
       int it;
-      int ws = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk);
+      int ws = walk_core<N>(S, P, xD, xL, type, prim, x, it, stk, chain_offs(E, c));
       if (ws != ST_CONVERGED && ws != ST_NEEDS_FP64) continue;
       bool m = true;
 #pragma unroll
@@ -192,15 +193,15 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, Walk
       if (c >= 0) {
         ++k;
         const uint64_t trial = 1 + (uint64_t)r * io.max_trials + (uint64_t)(k - 1);
-        if (sample_seed<N>(S, g, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, w.prim, w.x, stk) ==
-            0) {
+        if (sample_seed<N>(S, g, P, type, obj1, xD, nD, io.seed, (uint64_t)c, trial, io.alpha, w.prim, w.x, stk,
+                           chain_offs(E, c)) == 0) {
           walk_begin<N>(S, w);
           walking = true;
         }
       }
     }
     if (c >= 0 && walking) {
-      const int st = walk_step<N>(S, P, xD, xL, type, w, stk);
+      const int st = walk_step<N>(S, P, xD, xL, type, w, stk, chain_offs(E, c));
       if (st >= 0) {
         walking = false;
         bool m = st == ST_CONVERGED || st == ST_NEEDS_FP64;

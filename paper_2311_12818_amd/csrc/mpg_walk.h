@@ -59,7 +59,8 @@ __device__ __forceinline__ void walk_one(const DevScene& S, const WalkParams& P,
   const int type = E.type[c];
   const bool seed_ok = load_seed<N>(S, E, io, c, type, prim, x);
   int status = ST_SEED_INVALID, it = 0;
-  if (seed_ok) status = walk_core<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.xL, E.N, c), type, prim, x, it, stk);
+  if (seed_ok)
+    status = walk_core<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.xL, E.N, c), type, prim, x, it, stk, chain_offs(E, c));
   store_walk<N>(E, io, c, status, it, seed_ok, prim, x);
 }
 
@@ -106,7 +107,8 @@ __device__ __forceinline__ void finish_one(const DevScene& S, const WalkParams& 
   }
   WalkOut R;
   R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
-  finish<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
+  finish<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R,
+            chain_offs(E, c));
   io.status[c] = (int8_t)R.status;
   if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
   if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
@@ -146,7 +148,8 @@ __device__ __forceinline__ void fp64_one(const DevScene& S, const WalkParams& P,
   }
   WalkOut R;
   R.sol = 0; R.G = 0.f; R.kappa = 0.f; R.resid = 0.f;
-  finish_fp64<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R);
+  finish_fp64<N>(S, P, ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), ld_pt(E.xL, E.N, c), E.type[c], prim, x, stk, R,
+                 chain_offs(E, c));
   io.status[c] = (int8_t)R.status;
   if (io.sol) io.sol[c] = R.status == ST_CONVERGED ? R.sol : 0;
   if (io.G) io.G[c] = R.status == ST_CONVERGED ? R.G : 0.f;
@@ -168,7 +171,7 @@ __device__ __forceinline__ void seed_one(const DevScene& S, const DevGuide* G, c
   int prim[N];
   f3 pos[N];
   int r = sample_seed<N>(S, G, P, E.type[c], E.obj1[c], ld_pt(E.xD, E.N, c), ld_pt(E.nD, E.N, c), seed,
-                         (uint64_t)c, trial, alpha, prim, pos, stk);
+                         (uint64_t)c, trial, alpha, prim, pos, stk, chain_offs(E, c));
   st[c] = (int8_t)r;
   const size_t NN = E.N;
 #pragma unroll

@@ -53,7 +53,7 @@ def gpu_walk(M, scene, prm, ep, prim, pos, st, ws=None):
     return g
 
 
-def assert_gpu_chains_admissible(osc, ep, g, scale, prm_o, tag, budget=1e-3):
+def assert_gpu_chains_admissible(osc, ep, g, scale, prm_o, tag, budget=1e-3, offsets=None):
     """Every chain the GPU reports converged, re-checked in FP64 at the GPU's
     own vertices: it polishes to a residual below 1e-10 without moving more
     than the vertex tolerance, and the polished chain passes the side and
@@ -63,7 +63,8 @@ def assert_gpu_chains_admissible(osc, ep, g, scale, prm_o, tag, budget=1e-3):
     conv = g["status"] == 0
     idx = np.nonzero(conv)[0]
     sub = ep.subset(idx)
-    v = O.validate(osc, sub, g["prim"][:, idx], g["pos"][:, :, idx], prm=prm_o)
+    v = O.validate(osc, sub, g["prim"][:, idx], g["pos"][:, :, idx], prm=prm_o,
+                   offsets=None if offsets is None else np.ascontiguousarray(offsets[:, :, idx]))
     good = (v["ok"] == 1) & (v["residual"] < 1e-10) & (v["moved"] <= 1e-4 * scale) & (v["side"] == 1) & \
            (v["visible"] == 1)
     stats = dict(tag=tag, converged=int(conv.sum()), admissible=float(good.mean()),

@@ -134,3 +134,35 @@ def test_glossy_slab_chains_are_admissible_about_their_offsets(oracle_lib):
     conv = r["status"] == O.CONVERGED
     assert conv.mean() > 0.3
     assert r["residual"][conv].max() < 1e-10
+
+
+def test_glossy_jacobian_matches_central_differences(oracle_lib):
+    # the offset-normal constraint's Jacobian (sign turn and world-axis frame
+    # included) against central differences of the constraint itself
+    sc = W.slab_stack_scene()
+    osc = O.Scene(sc)
+    ep = W.slab_adjoint_endpoints(512, seed=12)
+    prm = O.params(sc.scale, cone_cos=math.cos(math.radians(W.SEED_CONE_DEG)))
+    off = O.sample_offsets(ep.n, seed=12, roughness=0.05)
+    prim, pos, st = O.sample_seeds(osc, ep, prm=prm, offsets=off)
+    checked = 0
+    for c in np.nonzero(st == 0)[0][:30]:
+        n = int(ep.length[c])
+        pr, p = prim[:n, c], pos[:, :n, c].T.copy()
+        o = off[:, :n, c].T.copy()
+        xD, xL = ep.xD[:, c].astype(np.float64), ep.xL[:, c].astype(np.float64)
+        C0, J, _ = O.constraint(osc, n, int(ep.types[c]), xD, xL, pr, p, offsets=o)
+        h = 1e-6
+        Jfd = np.zeros_like(J)
+        for k in range(2 * n):
+            y = np.zeros(2 * n)
+            y[k] = h
+            Cp, _, _ = O.constraint(osc, n, int(ep.types[c]), xD, xL, pr, O.offset_positions(osc, pr, p, y),
+                                    offsets=o)
+            y[k] = -h
+            Cm, _, _ = O.constraint(osc, n, int(ep.types[c]), xD, xL, pr, O.offset_positions(osc, pr, p, y),
+                                    offsets=o)
+            Jfd[:, k] = (Cp - Cm) / (2 * h)
+        assert np.abs(J - Jfd).max() < 1e-6 * max(1.0, np.abs(J).max())
+        checked += 1
+    assert checked > 20
