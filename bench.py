@@ -78,6 +78,10 @@ def parse():
                     help="chains of the forward+adjoint leg on the differentiation workload (0 = skip)")
     ap.add_argument("--configs-leg", type=int, default=1,
                     help="also time the sphere-mirror (4096) and icosphere (2^20) workloads in both forms")
+    ap.add_argument("--stree-n", type=int, default=1 << 22,
+                    help="configurations of the guided pass of the paper's-guide leg (0 = skip)")
+    ap.add_argument("--glossy-n", type=int, default=1 << 20,
+                    help="chains of the glossy-chain leg (0 = skip)")
     ap.add_argument("--per-length", type=int, default=1,
                     help="also time each chain length of the batch on its own (persistent form)")
     return ap.parse_args()
@@ -88,10 +92,16 @@ DEFAULT_N = {"sphere_mirror": 4096, "icosphere_tt": 1 << 20, "water_caustic": 1 
 MAX_LEN = {"sphere_mirror": 1, "icosphere_tt": 2, "water_caustic": 1, "slab_uneven": 8, "slab_adjoint": 4}
 
 
+# the sources the walk launch's kernels (bucketing, lane-refill walks, finish
+# passes) are compiled from: stored traffic counters apply while these hash
+# the same
+WALK_SOURCES = ("mpg_persistent.hip", "mpg_device.h", "mpg_internal.h", "mpg_walk.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_12818_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in WALK_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -253,6 +263,146 @@ def guide_leg(M, W, args):
     train["roofline"] = {"bound": "alu", "kernel": "fit_guide (k_em_*)", "achieved": e_ach, "peak": PEAK_FP32_TFLOPS,
                          "unit": "TFLOP/s", "frac": e_ach / PEAK_FP32_TFLOPS, "flops": em_flops}
     return {"workload": "water_caustic", "training": train, "guided": res}
+
+
+# 6-D root box of the paper's guide over the slab-stack configurations:
+# x_D in [0, 7.5] x [0, 4] x [-2.5, 0.5], x_L about the point light (2, 2, 3)
+STREE_LO = [0.0, 0.0, -2.5, 1.5, 1.5, 2.5]
+STREE_HI = [7.5, 4.0, 0.5, 2.5, 2.5, 3.5]
+
+
+def stree_leg(M, W, args, tuned):
+    """The paper's guide on the slab-stack configurations, lengths and types
+    drawn by the guide (prior P_0(n) = the batch's length law): two training
+    iterations of 2^20 configurations (guided seeds -> walk -> P(n)-factored
+    Bernoulli trials, at most 16 -> sample records -> tree fit), then a
+    guided pass of args.stree_n configurations with up to 64 trials per
+    converged chain.  Phases timed with HIP events; the fit (records to the
+    host, tree build, upload, footprint kernel) by the wall clock around the
+    synchronous call."""
+    import numpy as np
+    import torch
+    sc = W.slab_stack_scene()
+    scene = M.Scene(sc)
+    cone = math.cos(math.radians(W.SEED_CONE_DEG))
+    kw = dict(cone_cos=cone, max_len=8, defer_fp64=1, form=M.FORM_PERSISTENT)
+    for k in TUNED_KNOBS:
+        if k in tuned:
+            kw[k] = tuned[k] if k == "length_order" else int(tuned[k])
+    prm = M.walk_params(sc.scale, **kw)
+    p0 = np.array([0.4 * 0.6 ** (k - 1) for k in range(1, 8)] + [0.6 ** 7])
+    tree = M.STree(STREE_LO, STREE_HI, p0n=p0 / p0.sum(), alpha=0.5)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ws = M.Workspace(max(args.stree_n, 1 << 20))
+
+    def configs(n, seed):
+        ep = W.slab_uneven_endpoints(n, seed=seed)
+        ep.length[:] = 0
+        return M.Endpoints(ep)
+
+    def guided_pass(dep, seed, max_trials):
+        ev[0].record(stream)
+        n, ty, pn, prim, pos, st = M.sample_seeds_stree(scene, tree, dep, prm, seed=seed)
+        wep = M.Endpoints.from_tensors(dep.xD, dep.nD, dep.xL, n, ty, dep.obj1)
+        prim, pos, outs = M.manifold_walk_batch(scene, prm, wep, prim, pos, st, out_prim=prim, out_pos=pos, ws=ws)
+        ev[1].record(stream)
+        trials, ip, trunc, _ = M.estimate_inv_prob_stree(scene, tree, prm, wep, prim, pos, outs["status"],
+                                                         max_trials=max_trials, seed=seed + 1, ws=ws)
+        ev[2].record(stream)
+        rec = M.make_guide_records(wep, pos, outs, ip)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        conv = int((outs["status"] == M.CONVERGED).sum())
+        tw = int(trials.sum())
+        return rec, wep, (prim, pos, st, n), dict(
+            chains=dep.N, converged=conv, converged_fraction=conv / dep.N,
+            seeds_walk_ms=ev[0].elapsed_time(ev[1]), trials_ms=ev[1].elapsed_time(ev[2]),
+            records_ms=ev[2].elapsed_time(ev[3]), trial_walks=tw, truncated=int(trunc.sum()),
+            length_hist=np.bincount(n.cpu().numpy().astype(np.int64), minlength=9)[1:].tolist())
+
+    # warm-up of every kernel on a small batch (empty guide, then one fit)
+    rec, _, _, _ = guided_pass(configs(1 << 16, 900), 900, 16)
+    tree.fit(rec)
+    torch.cuda.synchronize()
+    tree = M.STree(STREE_LO, STREE_HI, p0n=p0 / p0.sum(), alpha=0.5)
+    training = []
+    for it in range(2):
+        rec, _, _, res = guided_pass(configs(1 << 20, 910 + it), 910 + it, 16)
+        t0 = time.perf_counter()
+        tree.fit(rec)
+        torch.cuda.synchronize()
+        res["fit_ms"] = 1e3 * (time.perf_counter() - t0)
+        res["tree"] = tree.stats()
+        training.append(res)
+    dep = configs(args.stree_n, 930)
+    _, wep, seeds, guided = guided_pass(dep, 930, 64)
+    guided["converged_walks_per_s"] = guided["converged"] / (guided["seeds_walk_ms"] / 1e3)
+    guided["trial_walks_per_s"] = guided["trial_walks"] / (guided["trials_ms"] / 1e3)
+    # roofline of the trial kernel: a trial is one guided seed draw plus one
+    # walk, priced at the counted work per walk of the guided batch (untimed
+    # counting walk over its first 2^18 configurations, at their drawn lengths)
+    m = min(dep.N, 1 << 18)
+    prim, pos, st, n = seeds
+    sub = M.Endpoints.from_tensors(wep.xD[:, :m].contiguous(), wep.nD[:, :m].contiguous(),
+                                   wep.xL[:, :m].contiguous(), wep.len[:m].contiguous(), wep.type[:m].contiguous(),
+                                   wep.obj1[:m].contiguous())
+    p2, q2, s2 = M.sample_seeds_stree(scene, tree, sub, prm, seed=930)[3:]
+    _, _, _, counts = M.walk_count(scene, M.walk_params(sc.scale, cone_cos=cone, max_len=8), sub, p2, q2, s2)
+    per_walk = sum(FLOPS_PER_UNIT[k] * counts[k] for k in FLOPS_PER_UNIT) / m
+    ach = guided["trial_walks"] * per_walk / (guided["trials_ms"] / 1e3) / 1e12
+    guided["roofline"] = {"bound": "alu", "kernel": "k_stree_inv_refill<n>", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                          "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "flops_per_trial_walk": per_walk}
+    return {"workload": "slab_uneven configurations, lengths and types drawn by the guide", "training": training,
+            "guided": guided}
+
+
+def glossy_leg(M, W, args, tuned):
+    """Glossy chains (GGX offset normals, roughness 0.05) on the
+    differentiation batch (2^20 chains of length 2..4 through the slab
+    stack): offsets + seeds + walk + FP64 pass, timed with HIP events, beside
+    the specular step on the same configurations."""
+    import torch
+    n = args.glossy_n
+    sc = W.slab_stack_scene()
+    scene = M.Scene(sc)
+    dep = M.Endpoints(W.slab_adjoint_endpoints(n))
+    cone = math.cos(math.radians(W.SEED_CONE_DEG))
+    kw = dict(cone_cos=cone, max_len=4, defer_fp64=1, form=M.FORM_PERSISTENT)
+    for k in TUNED_KNOBS:
+        if k in tuned:
+            kw[k] = tuned[k] if k == "length_order" else int(tuned[k])
+    prm = M.walk_params(sc.scale, **kw)
+    ws = M.Workspace(n)
+    prim, pos = M.empty_chains(n)
+    outs = M.walk_outputs(n)
+    off = torch.zeros((2, M.KMAX, n), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {"chains": n, "roughness": 0.05}
+    for label, glossy in (("specular", False), ("glossy", True)):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        reps = max(1, args.steps)
+        tot = [0.0, 0.0]
+        for rep in range(reps + 1):   # the first pass warms up
+            e[0].record(stream)
+            if glossy:
+                off.copy_(M.sample_offsets(n, seed=5, trial=rep, roughness=0.05))
+                dep.off = off
+            e[1].record(stream)
+            p, q, st = M.sample_seeds(scene, dep, prm, out=(prim, pos), ws=ws)
+            M.manifold_walk_batch(scene, prm, dep, p, q, st, out_prim=prim, out_pos=pos, outs=outs, ws=ws)
+            M.manifold_walk_fp64(scene, prm, dep, prim, pos, outs)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                tot[0] += e[0].elapsed_time(e[1])
+                tot[1] += e[1].elapsed_time(e[2])
+        dep.off = None
+        conv = int((outs["status"] == M.CONVERGED).sum())
+        ms = (tot[0] + tot[1]) / reps
+        res[label] = {"offsets_ms": tot[0] / reps, "step_ms": tot[1] / reps, "converged": conv,
+                      "converged_walks_per_s": conv / (ms / 1e3)}
+    return res
 
 
 def configs_leg(M, W, args):
@@ -530,6 +680,10 @@ def main():
     if args.guide_n > 0:
         forms["guided+trials"] = guide_leg(M, W, args)
     configs = configs_leg(M, W, args) if args.configs_leg else None
+    if args.stree_n > 0:
+        forms["stree_guide"] = stree_leg(M, W, args, load_tuned(args.tuned, "slab_uneven"))
+    if args.glossy_n > 0:
+        forms["glossy"] = glossy_leg(M, W, args, load_tuned(args.tuned, "slab_adjoint"))
 
     # untimed counting pass: algorithmic work of one walk launch
     prm_c = params("plain")

@@ -465,11 +465,17 @@ mpg_status sample_seeds_stree(const mpg_scene* scene, const mpg_stree* tree, con
  * max_trials + k - 1) and walks it; a trial matches when its tau equals
  * ep->d_type and its chain the target (same objects, vertices within
  * match_rel L).  d_trials = sum_r K_r, d_pn = P(n), d_inv_prob = mean_r K_r /
- * P(n) (P(n) factored out of the estimate).  Other targets get 0. */
+ * P(n) (P(n) factored out of the estimate).  Other targets, and targets
+ * longer than params->max_len, get 0; glossy offsets are not read.
+ * params->form = MPG_FORM_PERSISTENT with bucketing != 0 runs one lane-refill
+ * kernel per length over the targets bucketed in ws (capacity >= N, else
+ * MPG_ERR_INVALID_ARG); otherwise one thread per configuration and ws may be
+ * NULL.  Both forms give identical results. */
 mpg_status estimate_inv_prob_stree(const mpg_scene* scene, const mpg_stree* tree, const mpg_walk_params* params,
                                    const mpg_endpoints* ep, const mpg_chains* target, const int8_t* d_target_status,
                                    int32_t max_trials, int32_t repeats, uint64_t philox_seed, int32_t* d_trials,
-                                   float* d_inv_prob, uint8_t* d_truncated, float* d_pn, void* hip_stream);
+                                   float* d_inv_prob, uint8_t* d_truncated, float* d_pn, mpg_workspace* ws,
+                                   void* hip_stream);
 
 /* Sample records for fit_guide_stree from walked chains: {x_D, x_L, w_D =
  * normalize(x_1 - x_D), w, n, tau, 0 x 4} with w = T <1/P> (Eq. eq_weight),

@@ -500,7 +500,7 @@ def _declare_stree(L):
     L.sample_seeds_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.c_uint64,
                                      C.c_uint32, P, P, P, C.POINTER(mpg_chains), P, P]
     L.estimate_inv_prob_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
-                                          C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, P, P, P, P, P]
+                                          C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, P, P, P, P, P, P]
     L.make_guide_records.argtypes = [C.POINTER(mpg_endpoints), C.POINTER(mpg_chains), P, P, P, P, P, P]
     L.mpg_stree_active.argtypes = [P, C.POINTER(mpg_endpoints), P, P]
     for name in ["mpg_stree_desc_default", "mpg_stree_create", "mpg_stree_set_prior", "fit_guide_stree",
@@ -595,8 +595,10 @@ def sample_seeds_stree(scene: Scene, tree: STree, ep: Endpoints, params: mpg_wal
 
 
 def estimate_inv_prob_stree(scene: Scene, tree: STree, params: mpg_walk_params, ep: Endpoints, tprim, tpos, tstatus,
-                            max_trials=64, repeats=1, seed=0):
-    """Returns (trials, inv_prob = K / P(n), truncated, P(n)) as device tensors."""
+                            max_trials=64, repeats=1, seed=0, ws: Workspace = None):
+    """Returns (trials, inv_prob = K / P(n), truncated, P(n)) as device tensors
+    (persistent form: params.form = FORM_PERSISTENT with bucketing and a
+    workspace)."""
     torch = _torch()
     dev = ep.xD.device
     trials = torch.zeros(ep.N, dtype=torch.int32, device=dev)
@@ -606,7 +608,8 @@ def estimate_inv_prob_stree(scene: Scene, tree: STree, params: mpg_walk_params, 
     ch = mpg_chains(tprim.data_ptr(), tpos.data_ptr())
     _check(_slib().estimate_inv_prob_stree(scene.h, tree.h, C.byref(params), C.byref(ep.c()), C.byref(ch),
                                            tstatus.data_ptr(), int(max_trials), int(repeats), int(seed),
-                                           trials.data_ptr(), ip.data_ptr(), tr.data_ptr(), pn.data_ptr(), _stream()),
+                                           trials.data_ptr(), ip.data_ptr(), tr.data_ptr(), pn.data_ptr(),
+                                           ws.h if ws is not None else None, _stream()),
            "estimate_inv_prob_stree")
     return trials, ip, tr, pn
 

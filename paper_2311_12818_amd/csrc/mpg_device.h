@@ -804,7 +804,7 @@ __device__ __forceinline__ void sweep(const DevScene& S, vec3<T> xD, vec3<T> xL,
 // i's object.
 template <int N, class STK>
 __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x, const int* prim, const f3* dl,
-                                          float beta, const int* obj, float tmin, STK& stk, f3* xn, int* pn) {
+                                          float beta, float tmin, STK& stk, f3* xn, int* pn) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     f3 o = i == 0 ? xD : xn[i > 0 ? i - 1 : 0];
@@ -824,7 +824,9 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
     Hit h;
     if (!trace(S, o, d, excl, tmin, h, stk, bound, prim[i])) return false;
     if (h.prim == PRIM_NONE && !trace(S, o, d, excl, tmin, h, stk)) return false;
-    if (h.prim == PRIM_NONE || prim_obj(S, h.prim) != obj[i]) return false;
+    // the vertex stays on its object (looked up again rather than kept live
+    // through the walk)
+    if (h.prim == PRIM_NONE || prim_obj(S, h.prim) != prim_obj(S, prim[i])) return false;
     xn[i] = fmav(d, h.t, o);
     pn[i] = h.prim;
   }
@@ -842,7 +844,7 @@ __device__ __forceinline__ bool reproject(const DevScene& S, f3 xD, const f3* x,
 // Walk state of one chain between trial steps.
 template <int N>
 struct WalkState {
-  int prim[N], obj[N];
+  int prim[N];
   f3 x[N], dl[N];
   float beta, c2, step2;
   int it;
@@ -851,8 +853,6 @@ struct WalkState {
 
 template <int N>
 __device__ __forceinline__ void walk_begin(const DevScene& S, WalkState<N>& w) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) w.obj[i] = prim_obj(S, w.prim[i]);
   w.beta = 1.0f;
   w.it = 0;
   w.need_jac = true;
@@ -883,7 +883,7 @@ __device__ __forceinline__ int walk_step(const DevScene& S, const WalkParams& P,
   int pn[N];
   const bool small = w.step2 <= P.tol_step2;
   const float bt = small ? 1.0f : w.beta;
-  if (!reproject<N>(S, xD, w.x, w.prim, w.dl, bt, w.obj, P.tmin, stk, xn, pn)) {
+  if (!reproject<N>(S, xD, w.x, w.prim, w.dl, bt, P.tmin, stk, xn, pn)) {
     w.beta = 0.5f * bt;
     return -1;
   }

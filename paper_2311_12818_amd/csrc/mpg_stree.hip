@@ -200,6 +200,7 @@ struct StreeInvIO {
   float* pn;
   int max_trials, repeats;
   uint64_t seed;
+  int max_len;  // targets longer than this are left out (outputs 0)
 };
 
 template <int N, class STK>
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(256) k_stree_inv(DevScene S, DevSTree T, WalkP
   Stack stk = lane_stack(P.depth);
   if (c >= E.N) return;
   const int n = E.len[c];
-  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > KMAX || io.repeats < 1 || io.max_trials < 1) {
+  if (io.tstatus[c] != ST_CONVERGED || n < 1 || n > io.max_len || io.repeats < 1 || io.max_trials < 1) {
     io.trials[c] = 0;
     io.inv_prob[c] = 0.0f;
     io.pn[c] = 0.0f;
@@ -273,6 +274,160 @@ __global__ void __launch_bounds__(256) k_stree_inv(DevScene S, DevSTree T, WalkP
     case 6: stree_inv_one<6>(S, T, P, E, io, c, leaf, stk); break;
     case 7: stree_inv_one<7>(S, T, P, E, io, c, leaf, stk); break;
     default: stree_inv_one<8>(S, T, P, E, io, c, leaf, stk); break;
+  }
+}
+
+// Persistent form of the trials: targets bucketed by length, one kernel per
+// length in which every lane owns one target at a time and advances it by
+// one step per turn of the loop: a new trial (guided seed; a seed that fails
+// or draws another type ends the trial at once) or one walk step; a lane
+// whose target is done takes the next target of the bucket in the same
+// turn.  The trials of a target are the plain form's, in the same order, so
+// the results are identical.  Lanes waiting for a new trial start together
+// (at least half of the busy lanes, or no lane walking), so that their seed
+// rays are cast together.
+__global__ void __launch_bounds__(256) k_stree_classify(EpView E, StreeInvIO io, int8_t* cls) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= E.N) return;
+  const int n = E.len[c];
+  const bool target = io.tstatus[c] == ST_CONVERGED && n >= 1 && n <= io.max_len && io.repeats >= 1 &&
+                      io.max_trials >= 1;
+  cls[c] = (int8_t)(target ? n : 0);
+  if (!target) {
+    io.trials[c] = 0;
+    io.inv_prob[c] = 0.0f;
+    io.pn[c] = 0.0f;
+    if (io.truncated) io.truncated[c] = 0;
+  }
+}
+
+// At least two wavefronts per SIMD from length 3 up (the compiler's own
+// choice for lengths 5-8 is one, which leaves the length-8 bucket, the
+// longest trials, as the tail of the launch).
+constexpr int stree_trial_waves(int n) { return n >= 3 ? 2 : 1; }
+
+template <int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stree_trial_waves(N))))
+k_stree_inv_refill(DevScene S, DevSTree T, WalkParams P, EpView E, StreeInvIO io, int* ctr, const int* perm) {
+  Stack stk = lane_stack(P.depth);
+  const size_t NN = E.N;
+  const int start = ctr[CTR_OFF + N];
+  const int count = ctr[CTR_HIST + N];
+  int* head = &ctr[CTR_HEAD4 + N - 1];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int c = -1;
+  bool drained = false;
+  f3 tx[N];
+  int tobj[N];
+  f3 xD = {0.f, 0.f, 0.f}, nD = {0.f, 0.f, 1.f}, xL = {0.f, 0.f, 0.f};
+  int ttype = 0, obj1 = 0, leaf = 0;
+  int r = 0, k = 0, total = 0;
+  bool trunc = false, walking = false;
+  WalkState<N> w;
+  for (;;) {
+    const unsigned long long idle = __ballot(c < 0);
+    if (idle && !drained) {
+      const int nidle = __popcll(idle);
+      int base = 0;
+      if (lane == 0) base = atomicAdd(head, nidle);
+      base = __shfl(base, 0, 64);
+      if (c < 0) {
+        const int slot = base + __popcll(idle & below);
+        if (slot < count) {
+          c = perm[start + slot];
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            tx[i] = {io.tpos[(0 * KMAX + i) * NN + c], io.tpos[(1 * KMAX + i) * NN + c],
+                     io.tpos[(2 * KMAX + i) * NN + c]};
+            tobj[i] = prim_obj(S, io.tprim[i * NN + c]);
+          }
+          xD = ld_pt(E.xD, E.N, c);
+          nD = ld_pt(E.nD, E.N, c);
+          xL = ld_pt(E.xL, E.N, c);
+          ttype = E.type[c];
+          obj1 = E.obj1[c];
+          float q[6];
+          query6(E, c, q);
+          leaf = stree_leaf(T, q);
+          r = 0;
+          k = 0;
+          total = 0;
+          trunc = false;
+          walking = false;
+        }
+      }
+      if (base + nidle >= count) drained = true;
+    }
+    if (__ballot(c >= 0) == 0) {
+      if (drained) break;
+      continue;
+    }
+    const unsigned long long waiting = __ballot(c >= 0 && !walking);
+    const unsigned long long busy = __ballot(c >= 0);
+    const bool start_trials = 2 * __popcll(waiting) >= __popcll(busy);
+    bool finished = false;
+    if (c >= 0 && !walking && start_trials) {
+      if (k == io.max_trials) {  // no match within the budget: K = max_trials, truncated
+        trunc = true;
+        total += io.max_trials;
+        ++r;
+        k = 0;
+        finished = r == io.repeats;
+      }
+      if (!finished) {
+        ++k;
+        const uint64_t trial = 1 + (uint64_t)r * io.max_trials + (uint64_t)(k - 1);
+        const U8 U = philox_uniforms(io.seed, (uint64_t)c, trial, 0);
+        int type = 0;
+        if (stree_seed<N>(S, T, P, leaf, obj1, xD, nD, io.seed, (uint64_t)c, trial, U, w.prim, w.x, &type, stk) ==
+                0 &&
+            type == ttype) {
+          walk_begin<N>(S, w);
+          walking = true;
+        }
+      }
+    }
+    if (c >= 0 && walking) {
+      const int st = walk_step<N>(S, P, xD, xL, ttype, w, stk);
+      if (st >= 0) {
+        walking = false;
+        bool m = st == ST_CONVERGED || st == ST_NEEDS_FP64;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          f3 d = w.x[i] - tx[i];
+          m = m && prim_obj(S, w.prim[i]) == tobj[i] && dot(d, d) <= P.match2;
+        }
+        if (m) {
+          total += k;
+          ++r;
+          k = 0;
+          finished = r == io.repeats;
+        }
+      }
+    }
+    if (finished) {
+      const float pn = stree_pn(T, leaf, N);
+      io.trials[c] = total;
+      io.pn[c] = pn;
+      io.inv_prob[c] = pn > 0.0f ? (float)total / (float)io.repeats / pn : 0.0f;
+      if (io.truncated) io.truncated[c] = trunc ? 1 : 0;
+      c = -1;
+    }
+  }
+}
+
+typedef void (*stree_inv_kernel_t)(DevScene, DevSTree, WalkParams, EpView, StreeInvIO, int*, const int*);
+static stree_inv_kernel_t stree_inv_refill_kernel(int n) {
+  switch (n) {
+    case 1: return k_stree_inv_refill<1>;
+    case 2: return k_stree_inv_refill<2>;
+    case 3: return k_stree_inv_refill<3>;
+    case 4: return k_stree_inv_refill<4>;
+    case 5: return k_stree_inv_refill<5>;
+    case 6: return k_stree_inv_refill<6>;
+    case 7: return k_stree_inv_refill<7>;
+    default: return k_stree_inv_refill<8>;
   }
 }
 
@@ -544,7 +699,8 @@ extern "C" mpg_status estimate_inv_prob_stree(const mpg_scene* s, const mpg_stre
                                               const mpg_endpoints* ep, const mpg_chains* target,
                                               const int8_t* d_target_status, int32_t max_trials, int32_t repeats,
                                               uint64_t philox_seed, int32_t* d_trials, float* d_inv_prob,
-                                              uint8_t* d_truncated, float* d_pn, void* stream) {
+                                              uint8_t* d_truncated, float* d_pn, mpg_workspace* ws,
+                                              void* stream) {
   if (!s || !t) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob_stree: NULL scene or guide");
   WalkParams P;
   int waves;
@@ -557,11 +713,30 @@ extern "C" mpg_status estimate_inv_prob_stree(const mpg_scene* s, const mpg_stre
     return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob_stree: NULL argument");
   if (max_trials < 0 || repeats < 0) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob_stree: negative count");
   StreeInvIO io{target->d_prim, target->d_pos, d_target_status, d_trials, d_inv_prob, d_truncated, d_pn,
-                max_trials, repeats, philox_seed};
+                max_trials, repeats, philox_seed, std::min(std::max(p->max_len, 1), KMAX)};
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
-  hipLaunchKernelGGL(k_stree_inv, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
-                     s->dev, t->dev, P, E, io);
+  hipStream_t st0 = (hipStream_t)stream;
+  if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
+    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "estimate_inv_prob_stree: workspace too small");
+    int8_t* cls = (int8_t*)ws->aux;
+    hipLaunchKernelGGL(k_stree_classify, dim3((E.N + 255) / 256), dim3(256), 0, st0, E, io, cls);
+    HIP_TRY(hipGetLastError());
+    if ((st = bucket_classes(E.N, cls, ws, st0)) != MPG_OK) return st;
+    hipStream_t wk[MPG_WORKERS];
+    if ((st = workers_fork(st0, wk)) != MPG_OK) return st;
+    // the lengths the call may hold (1..max_len), longest first
+    for (int n = io.max_len, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+      stree_inv_kernel_t k = stree_inv_refill_kernel(n);
+      const int grid = resident_blocks((const void*)k, threads, lds);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, t->dev, P, E, io, ws->counters,
+                         (const int*)ws->perm);
+      HIP_TRY(hipGetLastError());
+    }
+    return workers_join(st0);
+  }
+  hipLaunchKernelGGL(k_stree_inv, dim3((E.N + threads - 1) / threads), dim3(threads), lds, st0, s->dev, t->dev, P,
+                     E, io);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }

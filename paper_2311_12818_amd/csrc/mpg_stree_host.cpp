@@ -13,7 +13,9 @@
 #include "mpg_stree_host.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 
 namespace mpg_host {
 
@@ -37,6 +39,78 @@ bool record_ok(const float* r, const double* lo, const double* hi) {
   return true;
 }
 
+// f(i) for i in [0, n) on up to `threads` threads (work items taken in
+// order from a shared counter; every item writes only its own outputs, so
+// the result does not depend on the schedule)
+template <class F>
+void parallel_for(int n, int threads, F f) {
+  threads = std::max(1, std::min(threads, n));
+  if (threads == 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    for (int i; (i = next.fetch_add(1)) < n;) f(i);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < threads; ++t) pool.emplace_back(worker);
+  worker();
+  for (std::thread& th : pool) th.join();
+}
+
+int host_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(h, 16u));
+}
+
+// one leaf's tables, before they are placed in the shared arrays
+struct LeafOut {
+  double W = 0.0, Wn[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int own = 0;
+  std::vector<int> grp_key, grp_count;
+  std::vector<float> grp_w, dir, cdf;
+  std::vector<int> sample;
+};
+
+void leaf_tables(const float* rec, const Work& lf, LeafOut* o) {
+  // (n, type, sample) order
+  std::vector<std::pair<long long, int>> key(lf.ids.size());
+  for (size_t e = 0; e < lf.ids.size(); ++e) {
+    const float* r = rec + 16 * (size_t)lf.ids[e];
+    const int n = (int)r[10], ty = (int)r[11] & 0xff;
+    o->W += r[9];
+    o->Wn[n - 1] += r[9];
+    o->own += lf.own[e] ? 1 : 0;
+    key[e] = {((long long)n << 40) | ((long long)ty << 32) | (long long)lf.ids[e], lf.ids[e]};
+  }
+  std::sort(key.begin(), key.end());
+  o->dir.reserve(3 * key.size());
+  o->cdf.reserve(key.size());
+  o->sample.reserve(key.size());
+  for (size_t i = 0; i < key.size();) {
+    size_t e = i;
+    const long long gk = key[i].first >> 32;
+    while (e < key.size() && (key[e].first >> 32) == gk) ++e;
+    double acc = 0.0;
+    for (size_t a = i; a < e; ++a) {
+      const float* r = rec + 16 * (size_t)key[a].second;
+      double dx = r[6], dy = r[7], dz = r[8];
+      double l = std::sqrt(dx * dx + dy * dy + dz * dz);
+      o->dir.push_back((float)(dx / l));
+      o->dir.push_back((float)(dy / l));
+      o->dir.push_back((float)(dz / l));
+      acc += r[9];
+      o->cdf.push_back((float)acc);
+      o->sample.push_back(key[a].second);
+    }
+    o->grp_key.push_back((int)((gk >> 8) & 0xff) | (int)((gk & 0xff) << 8));
+    o->grp_w.push_back((float)acc);
+    o->grp_count.push_back((int)(e - i));
+    i = e;
+  }
+}
+
 }  // namespace
 
 int build_stree(const float* rec, int n_rec, const StreeParams& prm, StreeHost* out) {
@@ -44,6 +118,7 @@ int build_stree(const float* rec, int n_rec, const StreeParams& prm, StreeHost* 
   out->leaf_W.clear(); out->leaf_Wn.clear(); out->leaf_own.clear(); out->leaf_groups.clear();
   out->grp_key.clear(); out->grp_w.clear(); out->grp_lobes.clear();
   out->lobe_dir.clear(); out->lobe_cdf.clear(); out->lobe_sample.clear();
+  const int threads = host_threads();
   std::vector<Work> nodes(1);
   Work& root = nodes[0];
   for (int a = 0; a < 6; ++a) { root.lo[a] = prm.lo[a]; root.hi[a] = prm.hi[a]; }
@@ -51,43 +126,84 @@ int build_stree(const float* rec, int n_rec, const StreeParams& prm, StreeHost* 
   for (int j = 0; j < n_rec; ++j)
     if (record_ok(rec + 16 * (size_t)j, prm.lo, prm.hi)) { root.ids.push_back(j); root.own.push_back(1); }
   const double limit = prm.thr_scale * std::sqrt((double)root.ids.size());
-  // breadth-first splitting; a node's index is its position in `nodes`
+  // Breadth-first splitting, one level at a time: the children of the i-th
+  // node split on a level are nodes end + 2i and end + 2i + 1 (end = first
+  // index after the level), the order a one-node-at-a-time breadth-first
+  // pass gives.  A node's entries are classified in chunks in parallel and
+  // the chunks concatenated in order, so each child lists its samples in the
+  // parent's order.
   std::vector<int> axis(1, -1), child(1, -1);
   std::vector<double> mid(1, 0.0);
-  for (size_t k = 0; k < nodes.size(); ++k) {
-    if (!((double)nodes[k].ids.size() > limit) || nodes[k].depth >= prm.max_depth) continue;
-    int ax = 0;
-    for (int a = 1; a < 6; ++a)
-      if (nodes[k].hi[a] - nodes[k].lo[a] > nodes[k].hi[ax] - nodes[k].lo[ax]) ax = a;
-    const double m = 0.5 * (nodes[k].lo[ax] + nodes[k].hi[ax]);
-    const double widen = prm.eps * (m - nodes[k].lo[ax]);
-    Work left, right;
-    for (int a = 0; a < 6; ++a) {
-      left.lo[a] = right.lo[a] = nodes[k].lo[a];
-      left.hi[a] = right.hi[a] = nodes[k].hi[a];
+  const size_t chunk = 1 << 15;
+  for (size_t a = 0, b = 1; a < b; a = b, b = nodes.size()) {
+    std::vector<int> split;
+    for (size_t k = a; k < b; ++k)
+      if ((double)nodes[k].ids.size() > limit && nodes[k].depth < prm.max_depth) split.push_back((int)k);
+    if (split.empty()) break;
+    struct Task { int s; size_t e0, e1; std::vector<int> lid, rid; std::vector<char> lown, rown; };
+    std::vector<Task> tasks;
+    std::vector<int> ax(split.size());
+    std::vector<double> m(split.size()), widen(split.size());
+    for (size_t i = 0; i < split.size(); ++i) {
+      const Work& w = nodes[split[i]];
+      int x = 0;
+      for (int q = 1; q < 6; ++q)
+        if (w.hi[q] - w.lo[q] > w.hi[x] - w.lo[x]) x = q;
+      ax[i] = x;
+      m[i] = 0.5 * (w.lo[x] + w.hi[x]);
+      widen[i] = prm.eps * (m[i] - w.lo[x]);
+      for (size_t e0 = 0; e0 < w.ids.size(); e0 += chunk)
+        tasks.push_back(Task{(int)i, e0, std::min(w.ids.size(), e0 + chunk), {}, {}, {}, {}});
     }
-    left.hi[ax] = m;
-    right.lo[ax] = m;
-    left.depth = right.depth = nodes[k].depth + 1;
-    const double lo_edge = nodes[k].lo[ax], hi_edge = nodes[k].hi[ax];
-    for (size_t e = 0; e < nodes[k].ids.size(); ++e) {
-      const int j = nodes[k].ids[e];
-      const double v = (double)rec[16 * (size_t)j + ax];
-      const bool mine = nodes[k].own[e] != 0;
-      if (v >= lo_edge - widen && v < m + widen) { left.ids.push_back(j); left.own.push_back(mine && v < m); }
-      if (v >= m - widen && v < hi_edge + widen) { right.ids.push_back(j); right.own.push_back(mine && v >= m); }
-    }
-    axis[k] = ax;
-    mid[k] = m;
-    child[k] = (int)nodes.size();
-    nodes[k].ids.clear();
-    nodes[k].ids.shrink_to_fit();
-    nodes[k].own.clear();
-    nodes.push_back(std::move(left));
-    nodes.push_back(std::move(right));
-    axis.push_back(-1); axis.push_back(-1);
-    child.push_back(-1); child.push_back(-1);
-    mid.push_back(0.0); mid.push_back(0.0);
+    parallel_for((int)tasks.size(), threads, [&](int t) {
+      Task& T = tasks[t];
+      const Work& w = nodes[split[T.s]];
+      const int x = ax[T.s];
+      const double mm = m[T.s], wd = widen[T.s], lo_edge = w.lo[x], hi_edge = w.hi[x];
+      T.lid.reserve(T.e1 - T.e0);
+      T.lown.reserve(T.e1 - T.e0);
+      T.rid.reserve(T.e1 - T.e0);
+      T.rown.reserve(T.e1 - T.e0);
+      for (size_t e = T.e0; e < T.e1; ++e) {
+        const int j = w.ids[e];
+        const double v = (double)rec[16 * (size_t)j + x];
+        const bool mine = w.own[e] != 0;
+        if (v >= lo_edge - wd && v < mm + wd) { T.lid.push_back(j); T.lown.push_back(mine && v < mm); }
+        if (v >= mm - wd && v < hi_edge + wd) { T.rid.push_back(j); T.rown.push_back(mine && v >= mm); }
+      }
+    });
+    nodes.resize(b + 2 * split.size());
+    axis.resize(nodes.size(), -1);
+    child.resize(nodes.size(), -1);
+    mid.resize(nodes.size(), 0.0);
+    // task ranges per split node (tasks are in split order)
+    std::vector<size_t> t0(split.size() + 1, 0);
+    for (const Task& T : tasks) ++t0[T.s + 1];
+    for (size_t i = 0; i < split.size(); ++i) t0[i + 1] += t0[i];
+    parallel_for((int)split.size(), threads, [&](int i) {
+      Work& w = nodes[split[i]];
+      Work& left = nodes[b + 2 * i];
+      Work& right = nodes[b + 2 * i + 1];
+      for (int q = 0; q < 6; ++q) {
+        left.lo[q] = right.lo[q] = w.lo[q];
+        left.hi[q] = right.hi[q] = w.hi[q];
+      }
+      left.hi[ax[i]] = m[i];
+      right.lo[ax[i]] = m[i];
+      left.depth = right.depth = w.depth + 1;
+      for (size_t t = t0[i]; t < t0[i + 1]; ++t) {
+        Task& T = tasks[t];
+        left.ids.insert(left.ids.end(), T.lid.begin(), T.lid.end());
+        left.own.insert(left.own.end(), T.lown.begin(), T.lown.end());
+        right.ids.insert(right.ids.end(), T.rid.begin(), T.rid.end());
+        right.own.insert(right.own.end(), T.rown.begin(), T.rown.end());
+      }
+      axis[split[i]] = ax[i];
+      mid[split[i]] = m[i];
+      child[split[i]] = (int)(b + 2 * i);
+      std::vector<int>().swap(w.ids);
+      std::vector<char>().swap(w.own);
+    });
   }
   const int nn = (int)nodes.size();
   out->axis = axis;
@@ -98,52 +214,42 @@ int build_stree(const float* rec, int n_rec, const StreeParams& prm, StreeHost* 
   out->leaf_Wn.assign((size_t)nn * 8, 0.0f);
   out->leaf_own.assign(nn, 0);
   out->leaf_groups.assign(nn, std::pair<int, int>(0, 0));
+  std::vector<LeafOut> lo(nn);
+  parallel_for(nn, threads, [&](int k) {
+    if (axis[k] < 0) leaf_tables(rec, nodes[k], &lo[k]);
+  });
+  // place every leaf's groups and lobes in node order
+  std::vector<size_t> g_off(nn + 1, 0), l_off(nn + 1, 0);
   for (int k = 0; k < nn; ++k) {
+    g_off[k + 1] = g_off[k] + lo[k].grp_key.size();
+    l_off[k + 1] = l_off[k] + lo[k].sample.size();
+  }
+  out->grp_key.resize(g_off[nn]);
+  out->grp_w.resize(g_off[nn]);
+  out->grp_lobes.resize(g_off[nn]);
+  out->lobe_dir.resize(3 * l_off[nn]);
+  out->lobe_cdf.resize(l_off[nn]);
+  out->lobe_sample.resize(l_off[nn]);
+  parallel_for(nn, threads, [&](int k) {
     out->mid[k] = (float)mid[k];
     out->depth[k] = nodes[k].depth;
-    if (axis[k] >= 0) continue;
-    const Work& lf = nodes[k];
-    double W = 0.0, Wn[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int own = 0;
-    // (n, type, sample) order
-    std::vector<std::pair<long long, int>> key(lf.ids.size());
-    for (size_t e = 0; e < lf.ids.size(); ++e) {
-      const float* r = rec + 16 * (size_t)lf.ids[e];
-      const int n = (int)r[10], ty = (int)r[11] & 0xff;
-      W += r[9];
-      Wn[n - 1] += r[9];
-      own += lf.own[e] ? 1 : 0;
-      key[e] = {((long long)n << 40) | ((long long)ty << 32) | (long long)lf.ids[e], lf.ids[e]};
+    if (axis[k] >= 0) return;
+    const LeafOut& L = lo[k];
+    out->leaf_W[k] = (float)L.W;
+    for (int q = 0; q < 8; ++q) out->leaf_Wn[(size_t)k * 8 + q] = (float)L.Wn[q];
+    out->leaf_own[k] = L.own;
+    out->leaf_groups[k] = std::pair<int, int>((int)g_off[k], (int)L.grp_key.size());
+    size_t first = l_off[k];
+    for (size_t g = 0; g < L.grp_key.size(); ++g) {
+      out->grp_key[g_off[k] + g] = L.grp_key[g];
+      out->grp_w[g_off[k] + g] = L.grp_w[g];
+      out->grp_lobes[g_off[k] + g] = std::pair<int, int>((int)first, L.grp_count[g]);
+      first += L.grp_count[g];
     }
-    std::sort(key.begin(), key.end());
-    out->leaf_W[k] = (float)W;
-    for (int q = 0; q < 8; ++q) out->leaf_Wn[(size_t)k * 8 + q] = (float)Wn[q];
-    out->leaf_own[k] = own;
-    const int g0 = (int)out->grp_key.size();
-    for (size_t i = 0; i < key.size();) {
-      size_t e = i;
-      const long long gk = key[i].first >> 32;
-      while (e < key.size() && (key[e].first >> 32) == gk) ++e;
-      const int first = (int)out->lobe_sample.size();
-      double acc = 0.0;
-      for (size_t a = i; a < e; ++a) {
-        const float* r = rec + 16 * (size_t)key[a].second;
-        double dx = r[6], dy = r[7], dz = r[8];
-        double l = std::sqrt(dx * dx + dy * dy + dz * dz);
-        out->lobe_dir.push_back((float)(dx / l));
-        out->lobe_dir.push_back((float)(dy / l));
-        out->lobe_dir.push_back((float)(dz / l));
-        acc += r[9];
-        out->lobe_cdf.push_back((float)acc);
-        out->lobe_sample.push_back(key[a].second);
-      }
-      out->grp_key.push_back((int)((gk >> 8) & 0xff) | (int)((gk & 0xff) << 8));
-      out->grp_w.push_back((float)acc);
-      out->grp_lobes.push_back(std::pair<int, int>(first, (int)(e - i)));
-      i = e;
-    }
-    out->leaf_groups[k] = std::pair<int, int>(g0, (int)out->grp_key.size() - g0);
-  }
+    std::copy(L.dir.begin(), L.dir.end(), out->lobe_dir.begin() + 3 * l_off[k]);
+    std::copy(L.cdf.begin(), L.cdf.end(), out->lobe_cdf.begin() + l_off[k]);
+    std::copy(L.sample.begin(), L.sample.end(), out->lobe_sample.begin() + l_off[k]);
+  });
   return nn;
 }
 

@@ -15,11 +15,12 @@ from . import (RENDER, STree, Endpoints, Scene, estimate_inv_prob_stree, make_gu
 
 def train_guide(scene: Scene, tree: STree, params, make_configs, budget: float, train_fraction: float = 0.3,
                 base_samples: int = 1 << 14, batch: int = 1 << 14, max_trials: int = 16, seed: int = 0,
-                clock=time.perf_counter):
+                clock=time.perf_counter, ws=None):
     """Runs the training stage.  make_configs(i, count) returns device
     Endpoints of `count` training configurations for batch i (lengths 0:
     drawn by the guide).  Returns a log with one entry per batch:
-    (iteration, samples, converged, refit, elapsed)."""
+    (iteration, samples, converged, refit, elapsed).  ws: a Workspace of at
+    least `batch` chains, needed when params select the persistent form."""
     import torch
     plan = mpg_train_plan(float(budget), float(train_fraction), int(base_samples))
     st = train_init(plan)
@@ -32,9 +33,10 @@ def train_guide(scene: Scene, tree: STree, params, make_configs, budget: float, 
         ep = make_configs(i, count)
         n, ty, pn, prim, pos, status = sample_seeds_stree(scene, tree, ep, params, seed=seed, trial=2 * i)
         wep = Endpoints.from_tensors(ep.xD, ep.nD, ep.xL, n, ty, ep.obj1)
-        prim, pos, outs = manifold_walk_batch(scene, params, wep, prim, pos, status, out_prim=prim, out_pos=pos)
+        prim, pos, outs = manifold_walk_batch(scene, params, wep, prim, pos, status, out_prim=prim, out_pos=pos,
+                                              ws=ws)
         _, ip, _, _ = estimate_inv_prob_stree(scene, tree, params, wep, prim, pos, outs["status"],
-                                              max_trials=max_trials, seed=seed + 1 + i)
+                                              max_trials=max_trials, seed=seed + 1 + i, ws=ws)
         records.append(make_guide_records(wep, pos, outs, ip))
         torch.cuda.synchronize()
         it = st.iteration

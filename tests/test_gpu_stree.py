@@ -209,3 +209,43 @@ def test_learned_guide_beats_the_initial_distribution(mpg):
     print(dict(rates=rates, tree=s), flush=True)
     assert s["leaves"] > 10
     assert rates[1] > rates[0] + 0.05
+
+
+def test_stree_trials_persistent_form_matches_plain(mpg):
+    """The lane-refill trial kernels (targets bucketed by length) give the
+    plain form's trials, P(n) and 1/P bit for bit, over lengths 1..8 drawn
+    by a fitted guide; targets longer than max_len get 0 in both forms."""
+    import torch
+    M = mpg
+    rec = synthetic_records(1 << 15, seed=4)
+    _, gt = both_trees(M, rec, p0n=geometric_prior(), alpha=0.5)
+    sc = W.slab_stack_scene()
+    scene = M.Scene(sc)
+    ep = W.slab_uneven_endpoints(20000, seed=45)
+    ep.length[:] = 0
+    dep = M.Endpoints(ep)
+    prm = M.walk_params(sc.scale, cone_cos=GC.cone_cos())
+    n, ty, pn, prim, pos, st = M.sample_seeds_stree(scene, gt, dep, prm, seed=13)
+    wep = M.Endpoints.from_tensors(dep.xD, dep.nD, dep.xL, n, ty, dep.obj1)
+    prim, pos, outs = M.manifold_walk_batch(scene, prm, wep, prim, pos, st, out_prim=prim, out_pos=pos)
+    ws = M.Workspace(ep.n)
+    for max_len in (8, 5):
+        plain = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), max_len=max_len)
+        pers = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), max_len=max_len, form=M.FORM_PERSISTENT, bucketing=1,
+                             refill=1)
+        a = M.estimate_inv_prob_stree(scene, gt, plain, wep, prim, pos, outs["status"], max_trials=16, seed=21)
+        b = M.estimate_inv_prob_stree(scene, gt, pers, wep, prim, pos, outs["status"], max_trials=16, seed=21, ws=ws)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert np.array_equal(GC.to_np(x), GC.to_np(y))
+        nn = GC.to_np(n)
+        conv = GC.to_np(outs["status"]) == M.CONVERGED
+        t = GC.to_np(a[0])
+        assert np.all(t[nn > max_len] == 0) and np.all(t[conv & (nn <= max_len)] >= 1)
+        hist = np.bincount(nn[conv].astype(np.int64), minlength=9)[1:]
+        print(dict(max_len=max_len, conv_by_length=hist.tolist(), mean_trials=float(t[conv & (nn <= max_len)].mean())),
+              flush=True)
+        assert (hist > 0).sum() >= 6
+    with pytest.raises(M.MPGError):
+        M.estimate_inv_prob_stree(scene, gt, pers, wep, prim, pos, outs["status"], max_trials=16, seed=21,
+                                  ws=M.Workspace(100))
