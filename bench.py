@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--compare-forms", type=int, default=1, help="also time the other form (fewer steps)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-config-seconds", type=float, default=4.0,
+                    help="host time of the oracle on each of the other configurations (0 = skip)")
     ap.add_argument("--tuned", default=os.path.join(ROOT, "paper_2311_12818_amd", "tuned.json"))
     ap.add_argument("--graph", type=int, default=1, help="also time the step captured into a HIP graph")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -145,22 +147,81 @@ def cpu_baseline(name, sc, full, seconds, single_thread_seconds=4.0):
 
     def run(nthreads, budget, chunk):
         done, conv, t0 = 0, 0, time.perf_counter()
+        per_n = {}
         while time.perf_counter() - t0 < budget and done < full.n:
             idx = np.arange(done, min(done + chunk, full.n))
             ep = full.subset(idx)
             prim, pos, st = O.sample_seeds(osc, ep, prm=prm, nthreads=nthreads)
             r = O.walk(osc, ep, prim, pos.astype(np.float32), st, prm=prm, nthreads=nthreads)
-            conv += int((r["status"] == O.CONVERGED).sum())
+            ok = r["status"] == O.CONVERGED
+            conv += int(ok.sum())
+            for k in np.unique(ep.length):
+                per_n[int(k)] = per_n.get(int(k), 0) + int((ok & (ep.length == k)).sum())
             done += len(idx)
-        return done, conv, time.perf_counter() - t0
+        return done, conv, time.perf_counter() - t0, per_n
 
-    done, conv, el = run(threads, seconds, 8192)
-    d1, c1, e1 = run(1, single_thread_seconds, 1024)
+    done, conv, el, per_n = run(threads, seconds, 8192)
+    d1, c1, e1, _ = run(1, single_thread_seconds, 1024)
     return {"value": conv / el, "unit": "converged walks/s", "cores": threads, "kind": "oracle",
+            "per_k": {str(k): v / el for k, v in sorted(per_n.items())},
             "sample": f"first {done} configurations of the same {name} batch (oracle p_0 seeds + FP64 walk + polish, "
                       f"{el:.1f} s on {threads} threads)",
             "attempted_walks_per_s": done / el, "single_thread_converged_walks_per_s": c1 / e1,
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def oracle_configs(seconds):
+    """The oracle on the other configurations, each for a bounded time on the
+    host's threads: the sphere mirror (all 4096 chains), the two-refraction
+    icosphere, the water surface with Bernoulli trials (p_0 seeds; up to 64
+    trials per converged chain) and the slab stack with the IFT gradients of
+    every converged chain."""
+    import numpy as np
+
+    import oracle as O
+    import workloads as W
+    threads = min(16, os.cpu_count() or 1)
+    cone = math.cos(math.radians(W.SEED_CONE_DEG))
+    out = {}
+    cases = (("sphere_mirror", W.sphere_mirror_scene, lambda n: W.sphere_mirror_endpoints(n), 4096, "walk"),
+             ("icosphere_tt", W.icosphere_glass_scene, lambda n: W.icosphere_endpoints(n), 1 << 16, "walk"),
+             ("water_caustic", W.water_scene, lambda n: W.water_endpoints(n), 1 << 14, "trials"),
+             ("slab_adjoint", W.slab_stack_scene, lambda n: W.slab_adjoint_endpoints(n), 1 << 12, "adjoint"))
+    for name, scene_fn, ep_fn, full_n, kind in cases:
+        sc = scene_fn()
+        osc = O.Scene(sc)
+        prm = O.params(sc.scale, cone_cos=cone)
+        full = ep_fn(full_n)
+        r_all, g_all = W.loss_weights(full_n)
+        done = conv = extra = 0
+        chunk = 1024
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds and done < full.n:
+            idx = np.arange(done, min(done + chunk, full.n))
+            ep = full.subset(idx)
+            prim, pos, st = O.sample_seeds(osc, ep, prm=prm, nthreads=threads)
+            r = O.walk(osc, ep, prim, pos.astype(np.float32), st, prm=prm, nthreads=threads)
+            ok = r["status"] == O.CONVERGED
+            conv += int(ok.sum())
+            if kind == "trials":
+                t, _, _ = O.inv_prob(osc, ep, r["prim"], r["pos"], r["status"], max_trials=64, alpha=1.0, prm=prm,
+                                     nthreads=threads)
+                extra += int(t.sum())
+            elif kind == "adjoint":
+                O.adjoint(osc, ep, r["prim"], r["pos"], r["status"], r_all[:, :, idx], g_all[idx], prm=prm,
+                          nthreads=threads)
+                extra += int(ok.sum())
+            done += len(idx)
+        el = time.perf_counter() - t0
+        res = {"chains": done, "seconds": el, "converged_walks_per_s": conv / el, "attempted_walks_per_s": done / el}
+        if kind == "trials":
+            res["trial_walks"] = extra
+            res["note"] = "p_0 seeds (alpha = 1), seeds + walk + up to 64 trials per converged chain"
+        if kind == "adjoint":
+            res["gradients"] = extra
+            res["note"] = "seeds + walk + IFT gradients (x_D, x_L, 32 surface parameters) of converged chains"
+        out[name] = res
+    return out
 
 
 def graph_leg(M, prm, step, args, N):
@@ -303,7 +364,7 @@ def stree_leg(M, W, args, tuned):
 
     def guided_pass(dep, seed, max_trials):
         ev[0].record(stream)
-        n, ty, pn, prim, pos, st = M.sample_seeds_stree(scene, tree, dep, prm, seed=seed)
+        n, ty, pn, prim, pos, st = M.sample_seeds_stree(scene, tree, dep, prm, seed=seed, ws=ws)
         wep = M.Endpoints.from_tensors(dep.xD, dep.nD, dep.xL, n, ty, dep.obj1)
         prim, pos, outs = M.manifold_walk_batch(scene, prm, wep, prim, pos, st, out_prim=prim, out_pos=pos, ws=ws)
         ev[1].record(stream)
@@ -347,7 +408,7 @@ def stree_leg(M, W, args, tuned):
     sub = M.Endpoints.from_tensors(wep.xD[:, :m].contiguous(), wep.nD[:, :m].contiguous(),
                                    wep.xL[:, :m].contiguous(), wep.len[:m].contiguous(), wep.type[:m].contiguous(),
                                    wep.obj1[:m].contiguous())
-    p2, q2, s2 = M.sample_seeds_stree(scene, tree, sub, prm, seed=930)[3:]
+    p2, q2, s2 = M.sample_seeds_stree(scene, tree, sub, prm, seed=930, ws=ws)[3:]
     _, _, _, counts = M.walk_count(scene, M.walk_params(sc.scale, cone_cos=cone, max_len=8), sub, p2, q2, s2)
     per_walk = sum(FLOPS_PER_UNIT[k] * counts[k] for k in FLOPS_PER_UNIT) / m
     ach = guided["trial_walks"] * per_walk / (guided["trials_ms"] / 1e3) / 1e12
@@ -742,6 +803,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(name, sc, ep, args.cpu_seconds)
+        if args.oracle_config_seconds > 0:
+            out["cpu_baseline"]["configs"] = oracle_configs(args.oracle_config_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -453,11 +453,16 @@ mpg_status mpg_stree_download(const mpg_stree* tree, int32_t* axis, float* mid, 
  * follow by Eq. (deduction).  ep->d_type is not read.  Outputs: n
  * (d_len_out), tau (d_type_out), P(n) of the mixture (d_pn), the seed chain
  * and d_status (0, MPG_SEED_INVALID or MPG_BAD_INPUT).  Random numbers:
- * Philox4x64-10, key (philox_seed, 0), counters (chain, trial, 0..2, 0). */
+ * Philox4x64-10, key (philox_seed, 0), counters (chain, trial, 0..2, 0).
+ * params->form = MPG_FORM_PERSISTENT with bucketing != 0 draws the lengths
+ * first and samples each length's seeds in a kernel of its own over the
+ * configurations bucketed in ws (capacity >= N, else MPG_ERR_INVALID_ARG);
+ * otherwise one thread per configuration and ws may be NULL.  Both forms
+ * give identical seeds. */
 mpg_status sample_seeds_stree(const mpg_scene* scene, const mpg_stree* tree, const mpg_walk_params* params,
                               const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial, uint8_t* d_len_out,
                               uint8_t* d_type_out, float* d_pn, mpg_chains* out, int8_t* d_status,
-                              void* hip_stream);
+                              mpg_workspace* ws, void* hip_stream);
 
 /* Reciprocal probability with the guide (Sec. 5.8): for each target with
  * status MPG_CONVERGED, n = ep->d_len is kept and each trial draws (w_D,

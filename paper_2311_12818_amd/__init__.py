@@ -498,7 +498,7 @@ def _declare_stree(L):
     L.mpg_stree_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
     L.mpg_stree_download.argtypes = [P] * 13
     L.sample_seeds_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints), C.c_uint64,
-                                     C.c_uint32, P, P, P, C.POINTER(mpg_chains), P, P]
+                                     C.c_uint32, P, P, P, C.POINTER(mpg_chains), P, P, P]
     L.estimate_inv_prob_stree.argtypes = [P, P, C.POINTER(mpg_walk_params), C.POINTER(mpg_endpoints),
                                           C.POINTER(mpg_chains), P, I32, I32, C.c_uint64, P, P, P, P, P, P]
     L.make_guide_records.argtypes = [C.POINTER(mpg_endpoints), C.POINTER(mpg_chains), P, P, P, P, P, P]
@@ -577,9 +577,12 @@ class STree:
         return d
 
 
-def sample_seeds_stree(scene: Scene, tree: STree, ep: Endpoints, params: mpg_walk_params, seed=0, trial=0):
+def sample_seeds_stree(scene: Scene, tree: STree, ep: Endpoints, params: mpg_walk_params, seed=0, trial=0,
+                       ws: Workspace = None):
     """Seeds from the paper's guide.  Returns (n, tau, P(n), prim, pos, status)
-    as device tensors; ep.len holds the fixed lengths (0 = sampled)."""
+    as device tensors; ep.len holds the fixed lengths (0 = sampled).
+    Persistent form: params.form = FORM_PERSISTENT with bucketing and a
+    workspace."""
     torch = _torch()
     dev = ep.xD.device
     n = torch.zeros(ep.N, dtype=torch.uint8, device=dev)
@@ -590,7 +593,7 @@ def sample_seeds_stree(scene: Scene, tree: STree, ep: Endpoints, params: mpg_wal
     ch = mpg_chains(prim.data_ptr(), pos.data_ptr())
     _check(_slib().sample_seeds_stree(scene.h, tree.h, C.byref(params), C.byref(ep.c()), int(seed), int(trial),
                                       n.data_ptr(), ty.data_ptr(), pn.data_ptr(), C.byref(ch), st.data_ptr(),
-                                      _stream()), "sample_seeds_stree")
+                                      ws.h if ws is not None else None, _stream()), "sample_seeds_stree")
     return n, ty, pn, prim, pos, st
 
 

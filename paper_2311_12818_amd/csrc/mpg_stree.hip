@@ -155,27 +155,42 @@ __device__ __forceinline__ void stree_seed_one(const DevScene& S, const DevSTree
   }
 }
 
-__global__ void __launch_bounds__(256) k_stree_seeds(DevScene S, DevSTree T, WalkParams P, EpView E, uint64_t seed,
-                                                     uint64_t trial, SeedOut o) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  Stack stk = lane_stack(P.depth);
-  if (c >= E.N) return;
+// The configuration's leaf and length: n = ep->d_len[c] when it is 1..8,
+// else drawn from the leaf; false for non-finite inputs or a fixed length
+// above 8.
+__device__ __forceinline__ bool stree_config(const DevSTree& T, const EpView& E, int c, uint64_t seed,
+                                             uint64_t trial, int* leaf, U8* U, int* n) {
   float q[6];
   query6(E, c, q);
   const int nfix = E.len[c];
   bool ok = nfix <= KMAX;
   for (int a = 0; a < 6; ++a) ok = ok && isfinite(q[a]);
   ok = ok && finite3(ld_pt(E.nD, E.N, c));
-  if (!ok) {
-    o.status[c] = ST_BAD_INPUT;
-    o.len[c] = 0;
-    o.type[c] = 0;
-    o.pn[c] = 0.0f;
+  if (!ok) return false;
+  *leaf = stree_leaf(T, q);
+  *U = philox_uniforms(seed, (uint64_t)c, trial, 0);
+  *n = nfix >= 1 ? nfix : stree_length(T, *leaf, *U);
+  return true;
+}
+
+__device__ __forceinline__ void stree_bad_input(const SeedOut& o, int c) {
+  o.status[c] = ST_BAD_INPUT;
+  o.len[c] = 0;
+  o.type[c] = 0;
+  o.pn[c] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_stree_seeds(DevScene S, DevSTree T, WalkParams P, EpView E, uint64_t seed,
+                                                     uint64_t trial, SeedOut o) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  Stack stk = lane_stack(P.depth);
+  if (c >= E.N) return;
+  int leaf, n;
+  U8 U;
+  if (!stree_config(T, E, c, seed, trial, &leaf, &U, &n)) {
+    stree_bad_input(o, c);
     return;
   }
-  const int leaf = stree_leaf(T, q);
-  const U8 U = philox_uniforms(seed, (uint64_t)c, trial, 0);
-  const int n = nfix >= 1 ? nfix : stree_length(T, leaf, U);
   o.len[c] = (uint8_t)n;
   o.pn[c] = stree_pn(T, leaf, n);
   switch (n) {
@@ -187,6 +202,62 @@ __global__ void __launch_bounds__(256) k_stree_seeds(DevScene S, DevSTree T, Wal
     case 6: stree_seed_one<6>(S, T, P, E, c, leaf, seed, trial, U, o, stk); break;
     case 7: stree_seed_one<7>(S, T, P, E, c, leaf, seed, trial, U, o, stk); break;
     default: stree_seed_one<8>(S, T, P, E, c, leaf, seed, trial, U, o, stk); break;
+  }
+}
+
+// Persistent form of the seeds: the lengths are drawn first (class = n, 0
+// for bad inputs, whose outputs are written here), the configurations
+// bucketed by length, and each length's seeds drawn by a kernel of its own
+// (same leaf, uniforms and length as the plain form, so the same seeds).
+__global__ void __launch_bounds__(256) k_stree_draw(DevSTree T, EpView E, uint64_t seed, uint64_t trial, SeedOut o,
+                                                    int8_t* cls) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= E.N) return;
+  int leaf, n;
+  U8 U;
+  if (!stree_config(T, E, c, seed, trial, &leaf, &U, &n)) {
+    stree_bad_input(o, c);
+    cls[c] = 0;
+    return;
+  }
+  o.len[c] = (uint8_t)n;
+  o.pn[c] = stree_pn(T, leaf, n);
+  cls[c] = (int8_t)n;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_stree_seeds_persist(DevScene S, DevSTree T, WalkParams P, EpView E,
+                                                             uint64_t seed, uint64_t trial, SeedOut o, int* ctr,
+                                                             const int* perm) {
+  Stack stk = lane_stack(P.depth);
+  const int start = ctr[CTR_OFF + N];
+  const int end = ctr[CTR_OFF + N + 1];
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    const int base = next_batch(&ctr[CTR_HEAD3 + N - 1]);
+    if (start + base >= end) break;
+    const int c = perm[start + base + lane];
+    if (c >= 0) {
+      int leaf, n;
+      U8 U;
+      stree_config(T, E, c, seed, trial, &leaf, &U, &n);
+      stree_seed_one<N>(S, T, P, E, c, leaf, seed, trial, U, o, stk);
+    }
+  }
+}
+
+typedef void (*stree_seed_kernel_t)(DevScene, DevSTree, WalkParams, EpView, uint64_t, uint64_t, SeedOut, int*,
+                                    const int*);
+static stree_seed_kernel_t stree_seed_kernel(int n) {
+  switch (n) {
+    case 1: return k_stree_seeds_persist<1>;
+    case 2: return k_stree_seeds_persist<2>;
+    case 3: return k_stree_seeds_persist<3>;
+    case 4: return k_stree_seeds_persist<4>;
+    case 5: return k_stree_seeds_persist<5>;
+    case 6: return k_stree_seeds_persist<6>;
+    case 7: return k_stree_seeds_persist<7>;
+    default: return k_stree_seeds_persist<8>;
   }
 }
 
@@ -301,14 +372,9 @@ __global__ void __launch_bounds__(256) k_stree_classify(EpView E, StreeInvIO io,
   }
 }
 
-// At least two wavefronts per SIMD from length 3 up (the compiler's own
-// choice for lengths 5-8 is one, which leaves the length-8 bucket, the
-// longest trials, as the tail of the launch).
-constexpr int stree_trial_waves(int n) { return n >= 3 ? 2 : 1; }
-
 template <int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stree_trial_waves(N))))
-k_stree_inv_refill(DevScene S, DevSTree T, WalkParams P, EpView E, StreeInvIO io, int* ctr, const int* perm) {
+__global__ void __launch_bounds__(256) k_stree_inv_refill(DevScene S, DevSTree T, WalkParams P, EpView E,
+                                                          StreeInvIO io, int* ctr, const int* perm) {
   Stack stk = lane_stack(P.depth);
   const size_t NN = E.N;
   const int start = ctr[CTR_OFF + N];
@@ -675,7 +741,7 @@ extern "C" mpg_status mpg_stree_download(const mpg_stree* t, int32_t* axis, floa
 extern "C" mpg_status sample_seeds_stree(const mpg_scene* s, const mpg_stree* t, const mpg_walk_params* p,
                                          const mpg_endpoints* ep, uint64_t philox_seed, uint32_t trial,
                                          uint8_t* d_len_out, uint8_t* d_type_out, float* d_pn, mpg_chains* out,
-                                         int8_t* d_status, void* stream) {
+                                         int8_t* d_status, mpg_workspace* ws, void* stream) {
   if (!s || !t) return fail(MPG_ERR_INVALID_ARG, "sample_seeds_stree: NULL scene or guide");
   WalkParams P;
   int waves;
@@ -689,8 +755,27 @@ extern "C" mpg_status sample_seeds_stree(const mpg_scene* s, const mpg_stree* t,
   SeedOut o{d_len_out, d_type_out, d_pn, out->d_prim, out->d_pos, d_status};
   const int threads = 64 * waves;
   const size_t lds = (size_t)waves * P.depth * 64 * 4;
-  hipLaunchKernelGGL(k_stree_seeds, dim3((E.N + threads - 1) / threads), dim3(threads), lds, (hipStream_t)stream,
-                     s->dev, t->dev, P, E, philox_seed, (uint64_t)trial, o);
+  hipStream_t st0 = (hipStream_t)stream;
+  if (p->form == MPG_FORM_PERSISTENT && p->bucketing) {
+    if (!ws || ws->cap < E.N) return fail(MPG_ERR_INVALID_ARG, "sample_seeds_stree: workspace too small");
+    int8_t* cls = (int8_t*)ws->aux;
+    hipLaunchKernelGGL(k_stree_draw, dim3((E.N + 255) / 256), dim3(256), 0, st0, t->dev, E, philox_seed,
+                       (uint64_t)trial, o, cls);
+    HIP_TRY(hipGetLastError());
+    if ((st = bucket_classes(E.N, cls, ws, st0)) != MPG_OK) return st;
+    hipStream_t wk[MPG_WORKERS];
+    if ((st = workers_fork(st0, wk)) != MPG_OK) return st;
+    for (int n = KMAX, q = 0; n >= 1; --n, q = (q + 1) % MPG_WORKERS) {
+      stree_seed_kernel_t k = stree_seed_kernel(n);
+      const int grid = resident_blocks((const void*)k, threads, lds);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, wk[q], s->dev, t->dev, P, E, philox_seed,
+                         (uint64_t)trial, o, ws->counters, (const int*)ws->perm);
+      HIP_TRY(hipGetLastError());
+    }
+    return workers_join(st0);
+  }
+  hipLaunchKernelGGL(k_stree_seeds, dim3((E.N + threads - 1) / threads), dim3(threads), lds, st0, s->dev, t->dev, P,
+                     E, philox_seed, (uint64_t)trial, o);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }

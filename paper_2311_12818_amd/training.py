@@ -31,7 +31,7 @@ def train_guide(scene: Scene, tree: STree, params, make_configs, budget: float, 
     while st.phase != RENDER:
         count = batch if st.done >= st.target else min(batch, st.target - st.done)
         ep = make_configs(i, count)
-        n, ty, pn, prim, pos, status = sample_seeds_stree(scene, tree, ep, params, seed=seed, trial=2 * i)
+        n, ty, pn, prim, pos, status = sample_seeds_stree(scene, tree, ep, params, seed=seed, trial=2 * i, ws=ws)
         wep = Endpoints.from_tensors(ep.xD, ep.nD, ep.xL, n, ty, ep.obj1)
         prim, pos, outs = manifold_walk_batch(scene, params, wep, prim, pos, status, out_prim=prim, out_pos=pos,
                                               ws=ws)

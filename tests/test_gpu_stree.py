@@ -249,3 +249,34 @@ def test_stree_trials_persistent_form_matches_plain(mpg):
     with pytest.raises(M.MPGError):
         M.estimate_inv_prob_stree(scene, gt, pers, wep, prim, pos, outs["status"], max_trials=16, seed=21,
                                   ws=M.Workspace(100))
+
+
+def test_stree_seeds_persistent_form_matches_plain(mpg):
+    """Lengths drawn first, configurations bucketed by length, one seed
+    kernel per length: the same n, tau, P(n), seed chains and statuses as
+    one thread per configuration, including fixed lengths and bad inputs."""
+    import torch
+    M = mpg
+    rec = synthetic_records(1 << 15, seed=5)
+    _, gt = both_trees(M, rec, p0n=geometric_prior(), alpha=0.5)
+    sc = W.slab_stack_scene()
+    scene = M.Scene(sc)
+    ep = W.slab_uneven_endpoints(30000, seed=46)
+    ep.length[: 20000] = 0                    # drawn; the rest keep their fixed lengths
+    ep.xD[0, 7] = np.nan                      # bad inputs
+    ep.length[9] = 11
+    dep = M.Endpoints(ep)
+    plain = M.walk_params(sc.scale, cone_cos=GC.cone_cos())
+    pers = M.walk_params(sc.scale, cone_cos=GC.cone_cos(), form=M.FORM_PERSISTENT, bucketing=1, refill=1)
+    ws = M.Workspace(ep.n)
+    a = M.sample_seeds_stree(scene, gt, dep, plain, seed=17, trial=3)
+    b = M.sample_seeds_stree(scene, gt, dep, pers, seed=17, trial=3, ws=ws)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert np.array_equal(GC.to_np(x), GC.to_np(y), equal_nan=True)
+    st = GC.to_np(a[5])
+    assert st[7] == M.BAD_INPUT and st[9] == M.BAD_INPUT
+    assert np.array_equal(GC.to_np(a[0])[20000:][st[20000:] != M.BAD_INPUT], ep.length[20000:][st[20000:] != M.BAD_INPUT])
+    assert (st == 0).mean() > 0.5
+    drawn = GC.to_np(a[0])[:20000]
+    assert np.array_equal(np.unique(drawn[st[:20000] != M.BAD_INPUT]), np.arange(1, 9))
