@@ -14,9 +14,9 @@ LIB = os.path.join(HERE, "libmpg.so")
 SOURCES = ["mpg_adjoint_plain_a.hip", "mpg_adjoint_plain_b.hip", "mpg_adjoint_plain_c.hip", "mpg_count_a.hip",
            "mpg_count_b.hip", "mpg_count_c.hip", "mpg_persistent.hip", "mpg_lib.hip", "mpg_trials.hip",
            "mpg_adjoint.hip", "mpg_guide.hip", "mpg_adjoint_plain.hip", "mpg_count.hip", "mpg_params.hip",
-           "mpg_noalloc.hip", "mpg_stree.hip", "mpg_stree_host.cpp", "mpg_train.cpp", "mpg_glossy.hip", "mpg_scene.cpp"]
+           "mpg_noalloc.hip", "mpg_stree.hip", "mpg_stree_build.hip", "mpg_train.cpp", "mpg_glossy.hip", "mpg_scene.cpp"]
 HEADERS = ["mpg_device.h", "mpg_internal.h", "mpg_walk.h", "mpg_scene.h", "mpg_adjoint.h", "mpg_adjoint_plain.h",
-           "mpg_count.h", "mpg_stree_host.h"]
+           "mpg_count.h", "mpg_stree_build.h"]
 DEPS = SOURCES + HEADERS
 
 HIPCC_FLAGS = [

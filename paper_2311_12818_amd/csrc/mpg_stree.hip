@@ -5,10 +5,11 @@
 // neighbour footprint.  Seeds draw n (unless given) and (w_D, tau) from the
 // defensive one-sample mixtures alpha p_0 + (1 - alpha) p_e; the reciprocal
 // probability keeps n across trials and divides by the analytic P(n)
-// (Sec. 5.8).  The tree topology is built on the host (mpg_stree_host.cpp);
-// the footprints and everything per configuration run here.
+// (Sec. 5.8).  The tree is built from the sample records on the GPU
+// (mpg_stree_build.hip); the footprints and everything per configuration run
+// here.
 #include "mpg_internal.h"
-#include "mpg_stree_host.h"
+#include "mpg_stree_build.h"
 
 namespace {
 
@@ -656,51 +657,44 @@ extern "C" mpg_status fit_guide_stree(mpg_stree* t, const float* d_records, int3
   if (!t || (n_records > 0 && !d_records) || n_records < 0)
     return fail(MPG_ERR_INVALID_ARG, "fit_guide_stree: bad argument");
   hipStream_t stream = (hipStream_t)stream_;
-  std::vector<float> rec((size_t)n_records * 16);
-  if (n_records > 0) {
-    HIP_TRY(hipMemcpyAsync(rec.data(), d_records, rec.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-  }
-  mpg_host::StreeParams prm;
+  StreeBuildParams prm;
   for (int a = 0; a < 6; ++a) { prm.lo[a] = t->desc.lo[a]; prm.hi[a] = t->desc.hi[a]; }
   prm.eps = t->desc.eps;
   prm.thr_scale = t->desc.thr_scale;
   prm.max_depth = t->desc.max_depth;
-  mpg_host::StreeHost H;
-  const int nn = mpg_host::build_stree(rec.data(), n_records, prm, &H);
-  // device copies of the new tree (the previous one is released first)
+  // the new tree is built into arrays of its own; the previous one is
+  // released once the build has succeeded
+  std::vector<void*> fresh;
+  StreeBuilt B;
+  mpg_status st = stree_build_gpu(d_records, n_records, prm, fresh, &B, stream);
+  if (st != MPG_OK) {
+    free_all(fresh);
+    return st;
+  }
   HIP_TRY(hipStreamSynchronize(stream));
   free_all(t->allocs);
+  t->allocs.swap(fresh);
   std::memset(&t->dev, 0, sizeof(t->dev));
   stree_prior(t);
-  std::vector<int2> lg(nn), gl(H.grp_lobes.size());
-  for (int k = 0; k < nn; ++k) lg[k] = make_int2(H.leaf_groups[k].first, H.leaf_groups[k].second);
-  for (size_t g = 0; g < gl.size(); ++g) gl[g] = make_int2(H.grp_lobes[g].first, H.grp_lobes[g].second);
-  std::vector<float4> lobes(H.lobe_sample.size());
-  for (size_t j = 0; j < lobes.size(); ++j)
-    lobes[j] = make_float4(H.lobe_dir[3 * j], H.lobe_dir[3 * j + 1], H.lobe_dir[3 * j + 2], 0.0f);
-  hipError_t e;
-  if ((e = upload(t->allocs, &t->dev.axis, H.axis.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.mid, H.mid.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.child, H.child.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.W, H.leaf_W.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.Wn, H.leaf_Wn.data(), (size_t)nn * KMAX)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.own, H.leaf_own.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.leaf_groups, lg.data(), nn)) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.grp_key, H.grp_key.data(), H.grp_key.size())) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.grp_w, H.grp_w.data(), H.grp_w.size())) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.grp_lobes, gl.data(), gl.size())) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.lobe, lobes.data(), lobes.size())) != hipSuccess ||
-      (e = upload(t->allocs, &t->dev.lobe_cdf, H.lobe_cdf.data(), H.lobe_cdf.size())) != hipSuccess)
-    return fail(MPG_ERR_HIP, std::string("fit_guide_stree: ") + hipGetErrorString(e));
-  t->n_nodes = nn;
-  t->n_leaves = 0;
-  for (int k = 0; k < nn; ++k) t->n_leaves += H.axis[k] < 0 ? 1 : 0;
-  t->n_groups = (int)gl.size();
-  t->n_lobes = (int)lobes.size();
+  t->dev.axis = B.axis;
+  t->dev.mid = B.mid;
+  t->dev.child = B.child;
+  t->dev.W = B.W;
+  t->dev.Wn = B.Wn;
+  t->dev.own = B.own;
+  t->dev.leaf_groups = B.leaf_groups;
+  t->dev.grp_key = B.grp_key;
+  t->dev.grp_w = B.grp_w;
+  t->dev.grp_lobes = B.grp_lobes;
+  t->dev.lobe = B.lobe;
+  t->dev.lobe_cdf = B.lobe_cdf;
+  t->n_nodes = B.n_nodes;
+  t->n_leaves = B.n_leaves;
+  t->n_groups = B.n_groups;
+  t->n_lobes = B.n_lobes;
   if (t->n_groups > 0) {
     hipLaunchKernelGGL(k_stree_footprint, dim3(t->n_groups), dim3(256), 0, stream, t->dev.grp_lobes, t->n_groups,
-                       (float4*)t->dev.lobe, t->desc.sigma_min, t->desc.sigma_lone);
+                       B.lobe, t->desc.sigma_min, t->desc.sigma_lone);
     HIP_TRY(hipGetLastError());
   }
   t->fitted = 1;
