@@ -79,9 +79,12 @@ class mpg_guide_desc(C.Structure):
 
 
 def lib():
-    """Load libmpg.so; raise if it has not been built (there is no fallback)."""
+    """Load libmpg.so; raise if it has not been built (there is no fallback).
+    torch is imported first: with the library's HIP runtime initialised
+    before torch's, the library found no device on the GPU host."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise MPGError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
         L = C.CDLL(LIB_PATH)
