@@ -390,23 +390,30 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
   }
       MPG_CSWAP(0, 1) MPG_CSWAP(2, 3) MPG_CSWAP(0, 2) MPG_CSWAP(1, 3) MPG_CSWAP(1, 2)
 #undef MPG_CSWAP
-      if (tn[0] == INFINITY) {
+      const int nh = (tn[0] != INFINITY) + (tn[1] != INFINITY) + (tn[2] != INFINITY) + (tn[3] != INFINITY);
+      if (nh == 0) {
         if (sp == 0) {
           done = true;
           break;
         }
+        // pop: the entry below the top comes up from the LDS column (read
+        // unconditionally; when the stack is now empty the value is unused)
         ref = top;
-        if (--sp > 0) top = stk.base[(sp - 1) * 64];
+        --sp;
+        top = stk.base[(sp > 0 ? sp - 1 : 0) * 64];
       } else {
-#pragma unroll
-        for (int k = 3; k >= 1; --k) {
-          if (tn[k] != INFINITY) {
-            if (sp >= stk.depth) return false;
-            if (sp > 0) stk.base[(sp - 1) * 64] = top;
-            top = cr[k];
-            ++sp;
-          }
-        }
+        // descend into the nearest hit child, push the other m = nh - 1 hits
+        // farthest first.  The pushes' LDS stores are made unconditional:
+        // a store a push does not need goes to the first column entry above
+        // the new stack (free, and inside the column by the depth check).
+        const int m = nh - 1;
+        if (sp + m > stk.depth) return false;
+        const int spare = sp + m > 0 ? sp + m - 1 : 0;
+        stk.base[(m >= 1 && sp > 0 ? sp - 1 : spare) * 64] = top;
+        stk.base[(m >= 2 ? sp : spare) * 64] = nh == 4 ? cr[3] : cr[2];
+        stk.base[(m >= 3 ? sp + 1 : spare) * 64] = cr[2];
+        top = m >= 1 ? cr[1] : top;
+        sp += m;
         ref = cr[0];
       }
       // every lane still traversing holds a leaf: test them together
