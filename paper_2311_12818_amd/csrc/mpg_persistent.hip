@@ -8,7 +8,8 @@
 // 2. k_bucket_scan: one wave turns the histogram into bucket offsets, each
 //    bucket padded to a multiple of 64 so that a wavefront's batch never
 //    straddles two lengths; padding slots get -1; queue heads are zeroed.
-// 3. k_bucket_scatter: block-aggregated slot reservation, perm[] = chain ids
+// 3. k_bucket_scatter: workgroup-aggregated slot reservation over contiguous
+//    ranges of chains, perm[] = chain ids
 //    (bucketing = 2: ordered by spatial cell inside each bucket, see below).
 // 4. One persistent kernel per length N (its own register budget), sized to
 //    the machine's occupancy; each wavefront pulls 64-slot batches from its
@@ -22,8 +23,9 @@ __global__ void __launch_bounds__(256) k_bucket_hist(EpView E, WalkIO io, int ma
   __shared__ int h[KMAX + 1];
   if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
   __syncthreads();
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < E.N) {
+  // grid-stride: a capped grid keeps the global atomics on the eight bins
+  // to a few per workgroup
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < E.N; c += gridDim.x * blockDim.x) {
     int n = E.len[c];
     bool ok = n >= 1 && n <= max_len && finite3(ld_pt(E.xD, E.N, c)) &&
               (!check_xl || finite3(ld_pt(E.xL, E.N, c))) && finite3(ld_pt(E.nD, E.N, c));
@@ -53,8 +55,8 @@ __global__ void __launch_bounds__(256) k_class_hist(int N, const int8_t* cls, in
   __shared__ int h[KMAX + 1];
   if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
   __syncthreads();
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < N && cls[c] > 0) atomicAdd(&h[(int)cls[c]], 1);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x)
+    if (cls[c] > 0) atomicAdd(&h[(int)cls[c]], 1);
   __syncthreads();
   if (threadIdx.x >= 1 && threadIdx.x <= KMAX && h[threadIdx.x]) atomicAdd(&ctr[CTR_HIST + threadIdx.x], h[threadIdx.x]);
 }
@@ -192,18 +194,37 @@ __global__ void k_bucket_scan(int* ctr, int* perm) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_bucket_scatter(int N, const int8_t* cls, int* ctr, int* perm) {
+// Each workgroup takes a contiguous range of per_block chains: it counts
+// their classes, reserves its slots in every bucket with one global atomic
+// per bucket, then writes the chains into them (LDS cursors).
+__global__ void __launch_bounds__(256) k_bucket_scatter(int N, const int8_t* cls, int* ctr, int* perm, int per_block) {
   __shared__ int cnt[KMAX + 1], base[KMAX + 1];
   if (threadIdx.x <= KMAX) cnt[threadIdx.x] = 0;
   __syncthreads();
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  int b = c < N ? cls[c] : 0;
-  int local = b > 0 ? atomicAdd(&cnt[b], 1) : 0;
+  const long long c0 = (long long)blockIdx.x * per_block;
+  const int c1 = (int)(c0 + per_block < N ? c0 + per_block : N);
+  for (int c = (int)c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const int b = cls[c];
+    if (b > 0) atomicAdd(&cnt[b], 1);
+  }
   __syncthreads();
-  if (threadIdx.x >= 1 && threadIdx.x <= KMAX && cnt[threadIdx.x])
-    base[threadIdx.x] = atomicAdd(&ctr[CTR_CUR + threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x >= 1 && threadIdx.x <= KMAX) {
+    const int k = threadIdx.x;
+    base[k] = cnt[k] ? ctr[CTR_OFF + k] + atomicAdd(&ctr[CTR_CUR + k], cnt[k]) : 0;
+    cnt[k] = 0;  // now the cursor of the bucket
+  }
   __syncthreads();
-  if (b > 0) perm[ctr[CTR_OFF + b] + base[b] + local] = c;
+  for (int c = (int)c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const int b = cls[c];
+    if (b > 0) perm[base[b] + atomicAdd(&cnt[b], 1)] = c;
+  }
+}
+
+// launch shape of the bucketing passes: at most 1024 workgroups of 256
+static int bucket_blocks(int N) { return std::max(1, std::min((N + 255) / 256, 1024)); }
+static int bucket_per_block(int N) {
+  const int g = bucket_blocks(N);
+  return ((N + g - 1) / g + 255) / 256 * 256;
 }
 
 
@@ -483,7 +504,8 @@ static mpg_status bucket_chains(int bucketing, int max_len, int check_xl, const 
   const int blocks = (E.N + 255) / 256;
   int* ctr = ws->counters;
   int8_t* cls = (int8_t*)ws->aux;
-  hipLaunchKernelGGL(k_bucket_hist, dim3(blocks), dim3(256), 0, stream, E, io, max_len, check_xl, ctr, cls);
+  hipLaunchKernelGGL(k_bucket_hist, dim3(bucket_blocks(E.N)), dim3(256), 0, stream, E, io, max_len, check_xl, ctr,
+                     cls);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
   HIP_TRY(hipGetLastError());
@@ -501,7 +523,8 @@ static mpg_status bucket_chains(int bucketing, int max_len, int check_xl, const 
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks), dim3(256), 0, stream, E, (const int8_t*)cls, (const int*)ctr,
                        cursor, ws->perm);
   } else {
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, E.N, (const int8_t*)cls, ctr, ws->perm);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(bucket_blocks(E.N)), dim3(256), 0, stream, E.N, (const int8_t*)cls, ctr,
+                       ws->perm, bucket_per_block(E.N));
   }
   HIP_TRY(hipGetLastError());
   return MPG_OK;
@@ -550,15 +573,15 @@ mpg_status seeds_persistent(const mpg_scene* s, const DevGuide& G, const WalkPar
 }
 
 mpg_status bucket_classes(int N, const int8_t* cls, mpg_workspace* ws, hipStream_t stream) {
-  const int blocks = (N + 255) / 256;
   int* ctr = ws->counters;
   hipLaunchKernelGGL(k_bucket_zero, dim3(1), dim3(MPG_WS_COUNTERS), 0, stream, ctr);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_class_hist, dim3(blocks), dim3(256), 0, stream, N, cls, ctr);
+  hipLaunchKernelGGL(k_class_hist, dim3(bucket_blocks(N)), dim3(256), 0, stream, N, cls, ctr);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, stream, ctr, ws->perm);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, stream, N, cls, ctr, ws->perm);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(bucket_blocks(N)), dim3(256), 0, stream, N, cls, ctr, ws->perm,
+                     bucket_per_block(N));
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }
