@@ -427,9 +427,12 @@ mpg_status mpg_stree_set_prior(mpg_stree* tree, const float* p0n, float alpha, f
  * its longest side; each child keeps its parent's samples inside its box
  * widened by eps of its extent along the split axis (Sec. 5.6).  Per leaf:
  * W, W_n; lobes grouped by (n, tau) with kappa = sigma^-2, sigma the angle to
- * the nearest other direction of the group, computed on the GPU.  The
- * records are copied to the host and the tree is built there: synchronous
- * on hip_stream; reallocates the guide's device memory. */
+ * the nearest other direction of the group.  The whole build runs on the
+ * GPU, level by level; the split and leaf decisions and the per-leaf and
+ * per-group weight sums are taken in FP64 in record order, so the tree does
+ * not depend on the launch shape.  Synchronous on hip_stream (each level's
+ * size steers the next level's launches); allocates the new tree and frees
+ * the old one only on success (on an error the guide is unchanged). */
 mpg_status fit_guide_stree(mpg_stree* tree, const float* d_records, int32_t n_records, void* hip_stream);
 
 /* Node, leaf, group and lobe counts of the fitted guide. */

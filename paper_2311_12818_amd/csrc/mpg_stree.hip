@@ -671,7 +671,10 @@ extern "C" mpg_status fit_guide_stree(mpg_stree* t, const float* d_records, int3
     free_all(fresh);
     return st;
   }
-  HIP_TRY(hipStreamSynchronize(stream));
+  if (hipStreamSynchronize(stream) != hipSuccess) {
+    free_all(fresh);
+    return fail(MPG_ERR_HIP, "fit_guide_stree: stream synchronisation failed");
+  }
   free_all(t->allocs);
   t->allocs.swap(fresh);
   std::memset(&t->dev, 0, sizeof(t->dev));
