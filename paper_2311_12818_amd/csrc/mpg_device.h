@@ -322,6 +322,14 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
             1.0f / (fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y)),
             1.0f / (fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z))};
   f3 oinv = {o.x * inv.x, o.y * inv.y, o.z * inv.z};
+  // Byte offsets, within a node, of the near and the far planes of the
+  // child boxes along each axis (the low plane is the near one where the
+  // direction is positive), fixed once per ray: the slab test then needs no
+  // min / max per axis.  With lo <= hi in every box the distances are the
+  // ones a min / max of both planes gives, bit for bit.
+  const uint32_t onx = inv.x < 0.0f ? 48u : 0u, ony = inv.y < 0.0f ? 64u : 16u, onz = inv.z < 0.0f ? 80u : 32u;
+  const uint32_t ofx = 48u - onx, ofy = 80u - ony, ofz = 112u - onz;
+  const char* node_bytes = reinterpret_cast<const char*>(S.nodes);
   if (cand >= 0 && cand < S.n_tris && cand != excl) {
     stk.tri();
     int4 id = S.tri_idx[cand];
@@ -361,27 +369,32 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
       // into the nearest hit child and push the others, farthest first
       if (ref >= S.n_nodes) return false;
       stk.box(4);
-      const float4* nd = S.nodes + 8 * (size_t)ref;
-      const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5];
-      const int4 ch = *reinterpret_cast<const int4*>(nd + 6);
+      const uint32_t nb = (uint32_t)ref << 7;
+      auto plane = [&](uint32_t off) { return *reinterpret_cast<const float4*>(node_bytes + (nb + off)); };
+      const float4 nx = plane(onx), ny = plane(ony), nz = plane(onz), fx = plane(ofx), fy = plane(ofy), fz = plane(ofz);
+      const int4 ch = *reinterpret_cast<const int4*>(node_bytes + (nb + 96u));
       float tn[4];
       int cr[4];
       {
-        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, lya[4] = {ly.x, ly.y, ly.z, ly.w};
-        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
-        const float hya[4] = {hy.x, hy.y, hy.z, hy.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+        const float nxa[4] = {nx.x, nx.y, nx.z, nx.w}, nya[4] = {ny.x, ny.y, ny.z, ny.w};
+        const float nza[4] = {nz.x, nz.y, nz.z, nz.w}, fxa[4] = {fx.x, fx.y, fx.z, fx.w};
+        const float fya[4] = {fy.x, fy.y, fy.z, fy.w}, fza[4] = {fz.x, fz.y, fz.z, fz.w};
         const int cha[4] = {ch.x, ch.y, ch.z, ch.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          float x0 = fmaf(lxa[k], inv.x, -oinv.x), x1 = fmaf(hxa[k], inv.x, -oinv.x);
-          float y0 = fmaf(lya[k], inv.y, -oinv.y), y1 = fmaf(hya[k], inv.y, -oinv.y);
-          float z0 = fmaf(lza[k], inv.z, -oinv.z), z1 = fmaf(hza[k], inv.z, -oinv.z);
-          float t0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
-          float t1 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), h.t));
+          float x0 = fmaf(nxa[k], inv.x, -oinv.x), x1 = fmaf(fxa[k], inv.x, -oinv.x);
+          float y0 = fmaf(nya[k], inv.y, -oinv.y), y1 = fmaf(fya[k], inv.y, -oinv.y);
+          float z0 = fmaf(nza[k], inv.z, -oinv.z), z1 = fmaf(fza[k], inv.z, -oinv.z);
+          float t0 = fmaxf(fmaxf(x0, y0), fmaxf(z0, tmin));
+          float t1 = fminf(fminf(x1, y1), fminf(z1, h.t));
           tn[k] = t0 <= t1 ? t0 : INFINITY;
           cr[k] = cha[k];
         }
       }
+      // the child references are needed only by a push; without this use
+      // (after the slab tests) the compiler issues their load inside the
+      // push branch, a second memory round trip per node
+      asm volatile("" : : "v"(ch.x), "v"(ch.y), "v"(ch.z), "v"(ch.w), "v"(tn[0]), "v"(tn[1]), "v"(tn[2]), "v"(tn[3]));
       // sort the four entry distances (misses at +infinity last)
 #define MPG_CSWAP(a, b)                                                     \
   if (tn[b] < tn[a]) {                                                      \
