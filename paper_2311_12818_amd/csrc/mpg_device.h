@@ -436,13 +436,29 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
       int start = leaf & 0xFFFFFF;
       int count = (leaf >> 24) & 0x7F;
       if (start + count > S.n_tris) return false;
-      for (int k = start; k < start + count; ++k) {
-        float4 v0 = S.tri_v[3 * (size_t)k], v1 = S.tri_v[3 * (size_t)k + 1], v2 = S.tri_v[3 * (size_t)k + 2];
-        int prim = __float_as_int(v0.w);
-        if (prim == excl) continue;
-        stk.tri();
-        float t = tri_test(rx, ry, rz, o, v0, v1, v2);
-        if (t > tmin) take(h, prim, t);
+      // the next triangle's vertices are loaded while this one is tested
+      // (the last iteration reloads its own, in bounds), and the excluded
+      // primitive is tested too and then dropped, so no load waits on a
+      // branch
+      const int end = start + count;
+      float4 v0, v1, v2;
+      if (count > 0) {
+        v0 = S.tri_v[3 * (size_t)start];
+        v1 = S.tri_v[3 * (size_t)start + 1];
+        v2 = S.tri_v[3 * (size_t)start + 2];
+      }
+      for (int k = start; k < end; ++k) {
+        const float4 a0 = v0, a1 = v1, a2 = v2;
+        const size_t kn = 3 * (size_t)(k + 1 < end ? k + 1 : k);
+        v0 = S.tri_v[kn];
+        v1 = S.tri_v[kn + 1];
+        v2 = S.tri_v[kn + 2];
+        const int prim = __float_as_int(a0.w);
+        const float t = tri_test(rx, ry, rz, o, a0, a1, a2);
+        if (prim != excl) {
+          stk.tri();
+          if (t > tmin) take(h, prim, t);
+        }
       }
       have_leaf = false;
     }
