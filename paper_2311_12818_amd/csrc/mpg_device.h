@@ -157,6 +157,8 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
 struct DevScene {
   const float4* nodes;      // 8 x float4 per 4-wide node: child boxes (SoA) + int4 child references + pad
   const float4* tri_v;      // 3 x float4 per triangle in BVH order; v0.w = primitive id (int bits)
+  const float4* tri_geo;    // 6 x float4 per triangle in primitive order: P0, P1, P2, N0, N1, N2 (unit);
+                            // P0.w = object, P1.w = material (int bits), P2.w = index of refraction
   const int4* tri_idx;      // [n_tris] vertex ids (i0, i1, i2) and object
   const float4* vpos;       // [n_verts]
   const float4* vnrm;       // [n_verts]
@@ -208,7 +210,10 @@ struct WalkParams {
 };
 
 __device__ __forceinline__ int prim_obj(const DevScene& S, int prim) {
-  return prim >= 0 ? S.tri_idx[prim].w : S.sphere_obj[-1 - prim];
+  return prim >= 0 ? __float_as_int(S.tri_geo[6 * (size_t)prim].w) : S.sphere_obj[-1 - prim];
+}
+__device__ __forceinline__ int prim_material(const DevScene& S, int prim) {
+  return prim >= 0 ? __float_as_int(S.tri_geo[6 * (size_t)prim + 1].w) : S.obj_info[S.sphere_obj[-1 - prim]].x;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,8 +337,8 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
   const char* node_bytes = reinterpret_cast<const char*>(S.nodes);
   if (cand >= 0 && cand < S.n_tris && cand != excl) {
     stk.tri();
-    int4 id = S.tri_idx[cand];
-    float t = tri_test(rx, ry, rz, o, S.vpos[id.x], S.vpos[id.y], S.vpos[id.z]);
+    const float4* tg = S.tri_geo + 6 * (size_t)cand;
+    float t = tri_test(rx, ry, rz, o, tg[0], tg[1], tg[2]);
     if (t > tmin) take(h, cand, t);
   }
   // traversal stack: the top entry lives in a register, the entries below it
@@ -525,11 +530,12 @@ template <typename T, bool DERIV>
 __device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> x, const ThetaDir* td = nullptr) {
   Geo<T> g;
   g.x = x;
-  int obj;
   if (prim < 0) {
     int s = -1 - prim;
     float4 sp = S.spheres[s];
-    obj = S.sphere_obj[s];
+    const int2 oi = S.obj_info[S.sphere_obj[s]];
+    g.mat = oi.x;
+    g.ior = (T)__int_as_float(oi.y);
     vec3<T> c = {(T)sp.x, (T)sp.y, (T)sp.z};
     vec3<T> d = x - c;
     T il = rsq(dot(d, d));
@@ -541,13 +547,20 @@ __device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> 
       g.dns_b = g.e2 * il;
     }
   } else {
-    int4 id = S.tri_idx[prim];
-    obj = id.w;
-    vec3<T> P0 = cvt<T>(ld3(S.vpos[id.x])), P1 = cvt<T>(ld3(S.vpos[id.y])), P2 = cvt<T>(ld3(S.vpos[id.z]));
-    vec3<T> N0 = cvt<T>(ld3(S.vnrm[id.x])), N1 = cvt<T>(ld3(S.vnrm[id.y])), N2 = cvt<T>(ld3(S.vnrm[id.z]));
-    theta_vertex(S, td, id.x, P0, N0);
-    theta_vertex(S, td, id.y, P1, N1);
-    theta_vertex(S, td, id.z, P2, N2);
+    const float4* tg = S.tri_geo + 6 * (size_t)prim;
+    const float4 q0 = tg[0], q1 = tg[1], q2 = tg[2];
+    vec3<T> P0 = cvt<T>(ld3(q0)), P1 = cvt<T>(ld3(q1)), P2 = cvt<T>(ld3(q2));
+    vec3<T> N0 = cvt<T>(ld3(tg[3])), N1 = cvt<T>(ld3(tg[4])), N2 = cvt<T>(ld3(tg[5]));
+    g.mat = __float_as_int(q1.w);
+    g.ior = (T)q2.w;
+    if constexpr (is_dual<T>::value) {
+      if (td) {
+        const int4 id = S.tri_idx[prim];
+        theta_vertex(S, td, id.x, P0, N0);
+        theta_vertex(S, td, id.y, P1, N1);
+        theta_vertex(S, td, id.z, P2, N2);
+      }
+    }
     vec3<T> E1 = P1 - P0, E2 = P2 - P0;
     T lenE1 = norm(E1);
     g.e1 = E1 * ((T)1 / lenE1);
@@ -570,9 +583,6 @@ __device__ __forceinline__ Geo<T> load_geo(const DevScene& S, int prim, vec3<T> 
       g.dns_b = (dnb - g.ns * dot(g.ns, dnb)) * il;
     }
   }
-  int2 oi = S.obj_info[obj];
-  g.mat = oi.x;
-  g.ior = (T)__int_as_float(oi.y);
   return g;
 }
 
@@ -585,8 +595,8 @@ __device__ __forceinline__ void load_frame(const DevScene& S, int prim, vec3<T> 
     vec3<T> c = {(T)sp.x, (T)sp.y, (T)sp.z};
     onb(normalize(x - c), e1, e2);
   } else {
-    int4 id = S.tri_idx[prim];
-    vec3<T> P0 = cvt<T>(ld3(S.vpos[id.x])), P1 = cvt<T>(ld3(S.vpos[id.y])), P2 = cvt<T>(ld3(S.vpos[id.z]));
+    const float4* tg = S.tri_geo + 6 * (size_t)prim;
+    vec3<T> P0 = cvt<T>(ld3(tg[0])), P1 = cvt<T>(ld3(tg[1])), P2 = cvt<T>(ld3(tg[2]));
     vec3<T> E1 = P1 - P0;
     e1 = normalize(E1);
     e2 = cross(normalize(cross(E1, P2 - P0)), e1);
@@ -1178,8 +1188,8 @@ __device__ __forceinline__ bool p0_point(const DevScene& S, const WalkParams& P,
   if (lo >= rg.y) lo = rg.y - 1;
   int prim = S.cdf_prim[rg.x + lo];
   if (prim >= 0) {
-    int4 id = S.tri_idx[prim];
-    f3 a = ld3(S.vpos[id.x]), b = ld3(S.vpos[id.y]), c = ld3(S.vpos[id.z]);
+    const float4* tg = S.tri_geo + 6 * (size_t)prim;
+    f3 a = ld3(tg[0]), b = ld3(tg[1]), c = ld3(tg[2]);
     float r = sqrtf(u2);
     pt = a * (1.0f - r) + b * (r * (1.0f - u3)) + c * (r * u3);
     return true;
@@ -1300,13 +1310,13 @@ __device__ __forceinline__ int deduce(const DevScene& S, const WalkParams& P, in
     prim[i] = h.prim;
     pos[i] = fmav(d, h.t, o);
     if (COINS) {
-      bool transmit = S.obj_info[prim_obj(S, h.prim)].x == MAT_DIELECTRIC && coins[i] < p_transmit;
+      bool transmit = prim_material(S, h.prim) == MAT_DIELECTRIC && coins[i] < p_transmit;
       type = transmit ? (type | (1 << i)) : (type & ~(1 << i));
     }
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    if (((type >> i) & 1) && S.obj_info[prim_obj(S, prim[i])].x != MAT_DIELECTRIC) return ST_SEED_INVALID;
+    if (((type >> i) & 1) && prim_material(S, prim[i]) != MAT_DIELECTRIC) return ST_SEED_INVALID;
   }
   if (COINS) *type_out = type;
   return 0;

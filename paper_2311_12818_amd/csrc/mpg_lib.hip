@@ -144,6 +144,21 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
     std::memcpy(&ib, &ior, 4);
     oi[o] = make_int2(d->obj_material[o], ib);
   }
+  // per-primitive geometry record (positions and unit normals of the three
+  // vertices, object, material and index of refraction): one load level for
+  // the walk's vertex geometry instead of triangle ids, then vertices
+  std::vector<float4> tg(6 * (size_t)d->n_tris);
+  for (int t = 0; t < d->n_tris; ++t) {
+    const int4 id = ti[t];
+    const int vid[3] = {id.x, id.y, id.z};
+    for (int v = 0; v < 3; ++v) {
+      tg[6 * (size_t)t + v] = vp[vid[v]];
+      tg[6 * (size_t)t + 3 + v] = vn[vid[v]];
+    }
+    std::memcpy(&tg[6 * (size_t)t].w, &id.w, 4);
+    std::memcpy(&tg[6 * (size_t)t + 1].w, &oi[id.w].x, 4);
+    std::memcpy(&tg[6 * (size_t)t + 2].w, &oi[id.w].y, 4);
+  }
   std::vector<float4> sph(d->n_spheres);
   for (int k = 0; k < d->n_spheres; ++k) {
     sph[k] = make_float4(d->spheres[4 * k], d->spheres[4 * k + 1], d->spheres[4 * k + 2], d->spheres[4 * k + 3]);
@@ -200,6 +215,7 @@ extern "C" mpg_status mpg_scene_create(const mpg_scene_desc* d, mpg_scene** out)
   if ((e = upload(s->allocs, &D.nodes, (const float4*)nodes.data(), nodes.size() / 4)) != hipSuccess) return bail(e, "nodes");
   if ((e = upload(s->allocs, &D.tri_v, tv.data(), tv.size())) != hipSuccess) return bail(e, "triangles");
   if ((e = upload(s->allocs, &D.tri_idx, ti.data(), ti.size())) != hipSuccess) return bail(e, "triangle ids");
+  if ((e = upload(s->allocs, &D.tri_geo, tg.data(), tg.size())) != hipSuccess) return bail(e, "triangle records");
   if ((e = upload(s->allocs, &D.vpos, vp.data(), vp.size())) != hipSuccess) return bail(e, "positions");
   if ((e = upload(s->allocs, &D.vnrm, vn.data(), vn.size())) != hipSuccess) return bail(e, "normals");
   if ((e = upload(s->allocs, &D.obj_info, oi.data(), oi.size())) != hipSuccess) return bail(e, "objects");

@@ -83,8 +83,10 @@ __global__ void k_zmax(const uint32_t* zmax_bits, float zmax_static, float* zmax
 }
 
 // triangle copies in BVH leaf order (first vertex carries the primitive id)
-__global__ void k_tri_copies(int n_tris, const int32_t* order, const int4* tri_idx, const float4* vpos, float4* tri_v,
-                             const int32_t* err) {
+// and the per-primitive geometry records (vertex positions keep the object,
+// material and index of refraction in their w slots; normals follow)
+__global__ void k_tri_copies(int n_tris, const int32_t* order, const int4* tri_idx, const float4* vpos,
+                             const float4* vnrm, float4* tri_v, float4* tri_geo, const int32_t* err) {
   if (*err != MPG_OK) return;
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tris) return;
@@ -94,6 +96,13 @@ __global__ void k_tri_copies(int n_tris, const int32_t* order, const int4* tri_i
   tri_v[3 * (size_t)k + 0] = make_float4(a.x, a.y, a.z, __int_as_float(t));
   tri_v[3 * (size_t)k + 1] = make_float4(b.x, b.y, b.z, 0.f);
   tri_v[3 * (size_t)k + 2] = make_float4(c.x, c.y, c.z, 0.f);
+  float4* g = tri_geo + 6 * (size_t)t;
+  g[0] = make_float4(a.x, a.y, a.z, tri_geo[6 * (size_t)t].w);
+  g[1] = make_float4(b.x, b.y, b.z, tri_geo[6 * (size_t)t + 1].w);
+  g[2] = make_float4(c.x, c.y, c.z, tri_geo[6 * (size_t)t + 2].w);
+  g[3] = vnrm[id.x];
+  g[4] = vnrm[id.y];
+  g[5] = vnrm[id.z];
 }
 
 __device__ __forceinline__ float wave_min(float v) {
@@ -204,7 +213,8 @@ extern "C" mpg_status mpg_scene_set_params(mpg_scene* s, const float* d_theta, i
   HIP_TRY(hipGetLastError());
   if (s->n_tris > 0) {
     hipLaunchKernelGGL(k_tri_copies, dim3((s->n_tris + 255) / 256), dim3(256), 0, stream, s->n_tris, s->order,
-                       D.tri_idx, D.vpos, (float4*)D.tri_v, (const int32_t*)s->param_err);
+                       D.tri_idx, D.vpos, D.vnrm, (float4*)D.tri_v, (float4*)D.tri_geo,
+                       (const int32_t*)s->param_err);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_refit, dim3((s->n_nodes + 3) / 4), dim3(256), 0, stream, s->n_nodes, s->ranges, D.tri_v,
                        (float*)D.nodes, s->pad, (const int32_t*)s->param_err);

@@ -23,7 +23,7 @@ __device__ __forceinline__ bool load_seed(const DevScene& S, const EpView& E, co
   if (seed_ok) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (((type >> i) & 1) && S.obj_info[prim_obj(S, prim[i])].x != MAT_DIELECTRIC) seed_ok = false;
+      if (((type >> i) & 1) && prim_material(S, prim[i]) != MAT_DIELECTRIC) seed_ok = false;
   }
   return seed_ok;
 }
