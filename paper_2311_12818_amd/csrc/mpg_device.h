@@ -452,6 +452,7 @@ __device__ bool trace(const DevScene& S, f3 o, f3 d, int excl, float tmin, Hit& 
         v1 = S.tri_v[3 * (size_t)start + 1];
         v2 = S.tri_v[3 * (size_t)start + 2];
       }
+#pragma unroll 2
       for (int k = start; k < end; ++k) {
         const float4 a0 = v0, a1 = v1, a2 = v2;
         const size_t kn = 3 * (size_t)(k + 1 < end ? k + 1 : k);
