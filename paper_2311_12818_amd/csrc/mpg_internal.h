@@ -58,8 +58,9 @@ struct mpg_scene {
 // within 512 / waves registers per lane and spills the rest.  A refill walk
 // spends most of its time waiting on ray-traversal loads, so more wavefronts
 // in flight outweigh the spill traffic: lengths 1-2 at 5 (96 registers,
-// against the compiler's own 4) and lengths 6-8 at 2 (256, against 1).
-constexpr int refill_waves(int n) { return n <= 2 ? 5 : (n >= 6 ? 2 : 1); }
+// against the compiler's own 4), length 3 at 4 (128, against 3), lengths
+// 4-5 at 3 (168, against 2) and lengths 6-8 at 2 (256, against 1).
+constexpr int refill_waves(int n) { return n <= 2 ? 5 : n == 3 ? 4 : n <= 5 ? 3 : 2; }
 
 // persistent form: counter words per workspace, spatial cells per length
 #define MPG_WS_COUNTERS 256
