@@ -150,9 +150,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// One wavefront per cell.  The cell's sample indices arrive in atomic order;
-// the initial means are the samples of rank floor((j + 1/2) m / K) in input
-// order, found by counting smaller indices.  Then em_iters iterations of
+// Input order within each cell: the scatter above leaves a cell's sample
+// indices in atomic order, which would make the EM sums depend on the run.
+// One wavefront per cell puts each index at its rank (the number of smaller
+// indices of the cell), writing the sorted order to a second array.
+__global__ void __launch_bounds__(256) k_em_sort(const int* offset, const int* order, int cells, int* sorted) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cell = blockIdx.x * 4 + wave;
+  if (cell >= cells) return;
+  const int beg = offset[cell], m = offset[cell + 1] - beg;
+  for (int k = lane; k < m; k += 64) {
+    const int idx = order[beg + k];
+    int rank = 0;
+    for (int q = 0; q < m; ++q) rank += order[beg + q] < idx;
+    sorted[beg + rank] = idx;
+  }
+}
+
+// One wavefront per cell, the cell's sample indices in input order.  The
+// initial means are the samples of rank floor((j + 1/2) m / K).  Then
+// em_iters iterations of
 //   E: r_ij = pi_j N(x_i; mu_j, S_j) / sum_k ...
 //   M: N_j = sum w r, mu_j = sum w r x / N_j,
 //      S_j = sum w r (x - mu_j)(x - mu_j)^T / N_j + reg I
@@ -199,20 +216,10 @@ __global__ void __launch_bounds__(256) k_em_cells(const float* samples, EMDesc D
   }
   cxx = wave_sum(cxx) / W + D.reg; cxy = wave_sum(cxy) / W; cyy = wave_sum(cyy) / W + D.reg;
   // initial means by rank in input order
-  for (int k = lane; k < m; k += 64) {
-    int idx = order[beg + k];
-    int rank = 0;
-    for (int q = 0; q < m; ++q) rank += order[beg + q] < idx;
-    for (int j = 0; j < K; ++j) {
-      int target = (2 * j + 1) * m / (2 * K);
-      if (rank == target) {
-        const float* r = samples + 8 * (size_t)idx;
-        P[j][1] = r[3];
-        P[j][2] = r[4];
-      }
-    }
-  }
   if (lane < K) {
+    const float* r = samples + 8 * (size_t)order[beg + (2 * lane + 1) * m / (2 * K)];
+    P[lane][1] = r[3];
+    P[lane][2] = r[4];
     P[lane][0] = 1.0f / K;
     P[lane][3] = cxx; P[lane][4] = cxy; P[lane][5] = cyy;
   }
@@ -306,8 +313,9 @@ extern "C" mpg_status fit_guide(const mpg_scene* s, const float* d_samples, int3
   for (int a = 0; a < 3; ++a) { D.lo[a] = g->desc.lo[a]; D.hi[a] = g->desc.hi[a]; }
   D.res = g->desc.res; D.comps = g->desc.comps; D.iters = g->desc.em_iters; D.min_samples = g->desc.min_samples;
   D.reg = g->desc.reg;
-  // scratch: per-sample cell (aux), order (perm), per-cell count (guide count),
-  // offsets and cursors (guide-owned scratch)
+  // scratch: per-sample cell (aux, then the order sorted within each cell),
+  // order (perm), per-cell count (guide count), offsets and cursors
+  // (guide-owned scratch)
   int* offset = g->scratch;
   int* cursor = g->scratch + cells + 1;
   hipLaunchKernelGGL(k_em_zero, dim3((cells + 255) / 256), dim3(256), 0, st, g->count, cells);
@@ -323,9 +331,13 @@ extern "C" mpg_status fit_guide(const mpg_scene* s, const float* d_samples, int3
     hipLaunchKernelGGL(k_em_scatter, dim3((n_samples + 255) / 256), dim3(256), 0, st, n_samples,
                        (const int*)ws->aux, (const int*)offset, cursor, ws->perm);
     HIP_TRY(hipGetLastError());
+    // the cell ids in aux are no longer needed: aux takes the sorted order
+    hipLaunchKernelGGL(k_em_sort, dim3((cells + 3) / 4), dim3(256), 0, st, (const int*)offset,
+                       (const int*)ws->perm, cells, ws->aux);
+    HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_em_cells, dim3((cells + 3) / 4), dim3(256), 0, st, d_samples, D, (const int*)offset,
-                     (const int*)ws->perm, cells, g->valid, g->pi, g->mu, g->cov, g->chol, g->count);
+                     (const int*)ws->aux, cells, g->valid, g->pi, g->mu, g->cov, g->chol, g->count);
   HIP_TRY(hipGetLastError());
   return MPG_OK;
 }

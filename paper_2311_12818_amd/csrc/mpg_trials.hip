@@ -125,8 +125,8 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, Walk
   const unsigned long long below = (1ull << lane) - 1ull;
   int c = -1;
   bool drained = false;
-  f3 tx[N];
-  int tobj[N];
+  // the target chain stays in memory (read back when a trial converges)
+  // rather than in 4 N registers held through every walk step
   f3 xD = {0.f, 0.f, 0.f}, nD = {0.f, 0.f, 1.f}, xL = {0.f, 0.f, 0.f};
   int type = 0, obj1 = 0;
   int r = 0, k = 0, total = 0;
@@ -143,12 +143,6 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, Walk
         const int slot = base + __popcll(idle & below);
         if (slot < count) {
           c = perm[start + slot];
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            tx[i] = {io.tpos[(0 * KMAX + i) * NN + c], io.tpos[(1 * KMAX + i) * NN + c],
-                     io.tpos[(2 * KMAX + i) * NN + c]};
-            tobj[i] = prim_obj(S, io.tprim[i * NN + c]);
-          }
           xD = ld_pt(E.xD, E.N, c);
           nD = ld_pt(E.nD, E.N, c);
           xL = ld_pt(E.xL, E.N, c);
@@ -205,10 +199,14 @@ __global__ void __launch_bounds__(256) k_inv_refill(DevScene S, DevGuide G, Walk
       if (st >= 0) {
         walking = false;
         bool m = st == ST_CONVERGED || st == ST_NEEDS_FP64;
+        if (m) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          f3 d = w.x[i] - tx[i];
-          m = m && prim_obj(S, w.prim[i]) == tobj[i] && dot(d, d) <= P.match2;
+          for (int i = 0; i < N; ++i) {
+            const f3 t = {io.tpos[(0 * KMAX + i) * NN + c], io.tpos[(1 * KMAX + i) * NN + c],
+                          io.tpos[(2 * KMAX + i) * NN + c]};
+            const f3 d = w.x[i] - t;
+            m = m && prim_obj(S, w.prim[i]) == prim_obj(S, io.tprim[i * NN + c]) && dot(d, d) <= P.match2;
+          }
         }
         if (m) {
           total += k;

@@ -108,6 +108,26 @@ def test_fit_guide_parity(mpg, res, n):
     assert abs(diff.mean()) <= 5e-3 and np.median(np.abs(diff)) <= 1e-4
 
 
+def test_fit_guide_is_deterministic(mpg):
+    # the samples of a cell are put in input order before the EM sums, so
+    # fits of the same records agree bit for bit whatever order the cell
+    # scatter's atomics left them in (and whatever the workspace held)
+    import torch
+    lo, hi = np.array(W.WATER_GRID_LO), np.array(W.WATER_GRID_HI)
+    a = torch.as_tensor(synth_samples(1 << 18, lo, hi, seed=5)).cuda()
+    b = torch.as_tensor(synth_samples(1 << 17, lo, hi, seed=6)).cuda()
+    ws = mpg.Workspace(1 << 18)
+    fits = []
+    for recs in (a, b, a):
+        gd = mpg.Guide(lo, hi, res=16, em_iters=30, scale=4.0)
+        mpg.fit_guide(None, recs, gd, ws)
+        torch.cuda.synchronize()
+        fits.append(gd.download())
+    for k in fits[0]:
+        assert np.array_equal(fits[0][k], fits[2][k], equal_nan=True), k
+    assert fits[0]["valid"].sum() > 100
+
+
 def test_fit_guide_empty_and_sparse(mpg):
     lo, hi = np.array([0.0, 0, 0]), np.array([1.0, 1, 1])
     samples = synth_samples(40, lo, hi)       # 40 samples over 8 cells: every cell below 16
